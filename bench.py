@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark: time to a 1e-8 relative residual of FP64 band-Lanczos block
+MINRES on one MI355X, plus the block operator's HBM bandwidth.
+
+A step is one complete solve A X = B (X_0 = 0, every block iteration of the
+hot path: block operator + Gram partials, reduction, band kernel, update
+pass) on inputs already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(A, p, nb):
+    """Algorithmic bytes per launch of the two streaming kernels (binary64
+    values, int32 indices): each input and output touched once."""
+    n, nnz = A.n, A.nnz
+    blk = 8 * n * p
+    pass1 = 12 * nnz + 4 * (n + 1) + 3 * blk + 8 * n * nb          # A, V_k, V_{k-1}, W out, bench in
+    pass2 = 8 * blk + 16 * n * nb                                  # W, V_k, V_{k+1}, M x3, X in/out, bench
+    spmm = 12 * nnz + 4 * (n + 1) + 2 * blk                        # A, V in, W out
+    return {"pass1_spmm_gram": pass1, "pass2_update": pass2, "spmm": spmm}
+
+
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "pass1_spmm_gram": ["paper_1301_2102_amd/csrc/kernels_spmm.hip", "paper_1301_2102_amd/csrc/bmr_internal.hpp"],
+    "pass2_update": ["paper_1301_2102_amd/csrc/kernels_stream.hip", "paper_1301_2102_amd/csrc/bmr_internal.hpp"],
+}
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
+    when it is missing or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(A, B, tol, gpu_iters, sample_iters):
+    """The CPU oracle, single BLAS thread, timed over a bounded prefix of the
+    same solve and scaled to the GPU's band-iteration count."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    As = A.to_scipy()
+    t0 = time.perf_counter()
+    r = oracle.solve(As, B, tol=tol, max_iter=sample_iters)
+    dt = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    per_iter = dt / max(r.iters, 1)
+    return {
+        "value": per_iter * gpu_iters,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"first {r.iters} band iterations of the same solve ({dt:.1f} s, {per_iter*1e3:.1f} ms per "
+                   f"band iteration, numpy/scipy with one thread), scaled to the {gpu_iters} band iterations "
+                   f"the GPU needs"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lap3d-128-p8")
+    ap.add_argument("--max-iter", type=int, default=0, help="override the band-iteration cap (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=32)
+    ap.add_argument("--spmm-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1301_2102_amd as bmr
+    from workloads import workload, rhs_normal
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    log(f"[bench] building workload {args.workload}")
+    A, B, tol, max_iter = workload(args.workload)
+    if args.max_iter:
+        max_iter = args.max_iter
+    n, p = B.shape
+    Ad = bmr.to_device(A, dev)
+    Bd = torch.from_numpy(B).to(dev)
+    X = torch.empty_like(Bd)
+    ws = torch.empty(bmr.workspace_bytes(n, p), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return bmr.solve(Ad, Bd, tol=tol, max_iter=max_iter, X=X, workspace=ws)[1]
+
+    for i in range(args.warmup):
+        info = step()
+        log(f"[bench] warmup {i}: {info.status_name} j={info.band_iters} {info.time_ms:.1f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    info = infos[-1]
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    log(f"[bench] timed {args.steps} solves: {ms_per_step:.2f} ms each, {info.status_name}, "
+        f"j={info.band_iters}, blocks={info.block_iters}")
+    beta = np.linalg.norm(B, axis=0)
+    explicit = float((bmr.residual(Ad, Bd, X) / beta).max())
+
+    # per-kernel durations inside a solve (HIP events on the solve stream)
+    _, pinfo = bmr.solve(Ad, Bd, tol=tol, max_iter=max_iter, workspace=ws, profile=True)
+    km = pinfo.kernel_ms
+    log(f"[bench] kernel ms per block iteration: {km}")
+    nbytes = kernel_bytes(A, p, 2)
+    dominant = max(("pass1_spmm_gram", "pass2_update"), key=lambda k: km[k])
+    achieved = nbytes[dominant] / (km[dominant] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dominant)
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes": nbytes[dominant], "avg_ms": round(km[dominant], 5)}
+    other = "pass2_update" if dominant == "pass1_spmm_gram" else "pass1_spmm_gram"
+    kernels = {k: {"avg_ms": round(km[k], 5),
+                   "GB/s": round(nbytes[k] / (km[k] * 1e-3) / 1e9, 1) if k in nbytes else None}
+               for k in ("pass1_spmm_gram", "reduce", "band", "pass2_update")}
+
+    # standalone block operator W = A V, p = 1, 8, 16 (same matrix)
+    spmm = {}
+    for q in (1, 8, 16):
+        V = torch.from_numpy(rhs_normal(n, q, seed=1)).to(dev)
+        W = torch.empty_like(V)
+        for _ in range(3):
+            bmr.spmm(Ad, V, W)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.spmm_reps):
+            bmr.spmm(Ad, V, W)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.spmm_reps
+        b = kernel_bytes(A, q, 0)["spmm"]
+        spmm[f"p{q}"] = {"avg_ms": round(ms, 5), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": b}
+        del V, W
+    log(f"[bench] spmm: {spmm}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle, {args.cpu_sample_iters} band iterations")
+        cpu = cpu_baseline(A, B, tol, info.band_iters, args.cpu_sample_iters)
+        log(f"[bench] cpu baseline {cpu}")
+
+    out = {
+        "metric": "time to 1e-8 rel. residual + SpMM HBM GB/s, 128^3 p=8; FP64 vs mixed",
+        "value": round(ms_per_step / 1e3, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "nnz": A.nnz, "p": p, "tol": tol, "max_iter": max_iter,
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "status": info.status_name,
+        "band_iters": info.band_iters,
+        "block_iters": info.block_iters,
+        "res_rec_max": float(info.res_rec.max()),
+        "res_explicit_max": explicit,
+        "roofline": roofline,
+        "kernels": kernels,
+        "spmm": spmm,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

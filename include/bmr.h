@@ -1,0 +1,168 @@
+/*
+ * bmr.h -- band-Lanczos block MINRES on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libbmr.so.  The library solves
+ *
+ *     A X = B,   A in R^{n x n} sparse, symmetric (indefinite),  B in R^{n x p},
+ *
+ * (the problem statement, eq. (1.1) of K. M. Soodhalter, "A block MINRES
+ * algorithm based on the band Lanczos method") by block MINRES over the band
+ * Lanczos basis: one basis vector per band iteration j, the operator applied
+ * to a block of p vectors every p iterations, dependent candidates replaced by
+ * pre-generated random vectors kept orthogonal to the basis, the band Hessenberg
+ * matrix reduced by Givens rotations and X updated progressively
+ * (Sections 3-5 and Algorithm 7.1 of the paper).
+ *
+ * Conventions shared by every entry point
+ *   - Precision: IEEE binary64 throughout.
+ *   - Blocks (B, X, V, W, R) are n x p, row-interleaved: element (i, c) is at
+ *     offset i*p + c.  This is a C-contiguous (n, p) array.
+ *   - A is CSR with int32 row pointers and column indices, column indices
+ *     sorted and unique within each row.  A must be symmetric; this is not
+ *     checked.
+ *   - Pointers documented as "device" must point to memory of the current
+ *     HIP device; "host" pointers to ordinary host memory.  The caller owns
+ *     all memory.  The library never allocates device memory: scratch comes
+ *     from the caller's workspace.
+ *   - All device work is enqueued on the given stream (NULL = legacy default
+ *     stream).  Entry points that return host results synchronise that
+ *     stream before returning.
+ *   - Return value: a bmr_status code.  Negative values are errors; on error
+ *     the contents of output arrays are unspecified.
+ */
+#ifndef BMR_H
+#define BMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BMR_VERSION 10000 /* 1.0.0 */
+#define BMR_MAX_P 16      /* largest block size p */
+#define BMR_MAX_BENCH 4   /* largest substitutes bench */
+
+enum bmr_status {
+  BMR_CONVERGED = 0,          /* max_i ||b_i - A x_i|| / ||b_i|| < tol (recurrence residual) */
+  BMR_MAX_ITER = 1,           /* max_iter band iterations done; X is the last iterate */
+  BMR_BENCH_EXHAUSTED = 2,    /* a dependent vector found no substitute; X is the last iterate */
+  BMR_INVALID_ARG = -1,       /* p outside [1, BMR_MAX_P], n < 1, NULL pointer, tol <= 0, ... */
+  BMR_WORKSPACE_TOO_SMALL = -2,
+  BMR_HIP_ERROR = -3,         /* a HIP runtime call failed */
+  BMR_NONFINITE = -4,         /* NaN or Inf in B or in a computed coefficient */
+  BMR_SINGULAR_R = -5         /* a diagonal entry of the band QR factor R is zero */
+};
+
+/* Sparse symmetric matrix, CSR.  All pointers are device pointers. */
+typedef struct bmr_csr {
+  int64_t n;                /* rows = columns, 1 <= n < 2^31 */
+  int64_t nnz;              /* stored entries, < 2^31 */
+  const int32_t* row_ptr;   /* n + 1 entries, row_ptr[0] = 0, row_ptr[n] = nnz */
+  const int32_t* col_idx;   /* nnz entries */
+  const double* val;        /* nnz entries */
+} bmr_csr_t;
+
+/* Solver options (Algorithm 7.1's eps and M, the dependence tolerance of
+ * Section 5 and the bench size of Section 5.1).  bmr_default_opts fills it. */
+typedef struct bmr_opts {
+  double tol;          /* eps > 0: stop when every column has recurrence residual
+                          ||b_i - A x_i|| / ||b_i|| < tol (columns with b_i = 0 count
+                          as converged with x_i = 0).  Default 1e-8. */
+  int64_t max_iter;    /* M >= 1: band iterations j (p per block iteration). Default 10000. */
+  double gamma;        /* dependence tolerance, relative: the candidate of iteration j
+                          is dependent when its norm after orthogonalisation is
+                          <= gamma * ||A u_j|| (initial QR: <= gamma * ||b_i||).
+                          Default 1e-10. */
+  int32_t n_bench;     /* substitute vectors, 0 .. BMR_MAX_BENCH.  Default 2. */
+  int32_t poll_every;  /* block iterations enqueued between host status polls; 0 = auto */
+  uint64_t seed;       /* seed of the substitute generator (SplitMix64).  Default 0. */
+  int64_t hist_cap;    /* rows of the residual history kept on the device (>= 0).
+                          Default 0. */
+  uint32_t flags;      /* BMR_FLAG_* bits.  Default 0. */
+  uint32_t _reserved;
+} bmr_opts_t;
+
+/* bmr_opts_t.flags: time every kernel of every block iteration with HIP
+ * events on the solve stream (one block iteration in flight at a time; the
+ * averages go to bmr_stats_t.t_kernel_ms). */
+#define BMR_FLAG_PROFILE 1u
+
+/* Host-side result summary. */
+typedef struct bmr_stats {
+  int32_t status;          /* enum bmr_status */
+  int32_t n_replaced;      /* basis vectors taken from the bench */
+  int64_t band_iters;      /* band iterations j performed */
+  int64_t block_iters;     /* operator applications (block iterations) */
+  int32_t n_explicit_qr;   /* block iterations whose new-block QR ran column by column */
+  int32_t p;
+  double res_rec[BMR_MAX_P];  /* final recurrence residual ||b_i - A x_i|| / ||b_i|| */
+  double time_ms;          /* wall time of the solve on the stream (HIP events) */
+  /* with BMR_FLAG_PROFILE: mean duration per block iteration of the four
+   * kernels (block operator pass, partial-sum reduction, band kernel, update
+   * pass) and the number of block iterations timed */
+  double t_kernel_ms[4];
+  int64_t n_profiled;
+} bmr_stats_t;
+
+/* Library version, BMR_VERSION of the build. */
+int bmr_version(void);
+
+/* Static, human-readable name of a status code. */
+const char* bmr_status_string(int status);
+
+/* Fill *opts with the defaults listed in bmr_opts_t.  opts: host. */
+void bmr_default_opts(bmr_opts_t* opts);
+
+/* Bytes of device workspace bmr_solve and bmr_residual need for a system of
+ * n rows, block size p and the given options (opts may be NULL for defaults).
+ * bytes: host output.  Returns BMR_INVALID_ARG for p outside [1, BMR_MAX_P],
+ * n < 1 or n_bench outside [0, BMR_MAX_BENCH]. */
+int bmr_workspace_bytes(int64_t n, int p, const bmr_opts_t* opts, size_t* bytes);
+
+/* Solve A X = B with X_0 = 0 (eq. (1.1); Algorithm 7.1 inputs and outputs).
+ *
+ *   A          host pointer to a bmr_csr_t whose arrays are on the device.
+ *   B          device, n x p row-interleaved, read only.
+ *   X          device, n x p row-interleaved, output (overwritten).  Must not
+ *              alias B or the workspace.
+ *   p          block size, 1 <= p <= BMR_MAX_P.
+ *   opts       host, may be NULL (defaults).
+ *   workspace  device, at least bmr_workspace_bytes(n, p, opts) bytes,
+ *              256-byte aligned; contents on entry are ignored.
+ *   stream     HIP stream all work is enqueued on.
+ *   stats      host, may be NULL.
+ *   res_hist   host, may be NULL; else at least opts->hist_cap * p doubles.
+ *              Row j-1 receives rho_j^{(i)} / ||b_i|| (eq. (3.5)) for band
+ *              iterations j = 1 .. min(band_iters, hist_cap); 0 where b_i = 0.
+ *
+ * The stream is synchronised before return.  Status: BMR_CONVERGED,
+ * BMR_MAX_ITER, BMR_BENCH_EXHAUSTED or an error code. */
+int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_opts_t* opts,
+              void* workspace, size_t workspace_bytes, hipStream_t stream, bmr_stats_t* stats,
+              double* res_hist);
+
+/* W = A V, the block operator application of Algorithm 7.1 (A applied to p
+ * vectors at once; each row of A is read once for all p columns).
+ * V, W: device, n x p row-interleaved, must not alias.  Asynchronous: returns
+ * after enqueueing on stream. */
+int bmr_spmm(const bmr_csr_t* A, const double* V, double* W, int p, hipStream_t stream);
+
+/* Explicit residual R = B - A X and its column norms (the quantity the
+ * stopping test of Algorithm 7.1 bounds).
+ *   B, X       device, n x p row-interleaved.
+ *   R          device n x p output, or NULL to compute the norms only.
+ *   norms      host, p doubles: ||b_i - A x_i||.
+ *   workspace  device, >= bmr_workspace_bytes(n, p, NULL) bytes.
+ * Synchronises the stream. */
+int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, double* R,
+                 double* norms, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMR_H */

@@ -1,0 +1,114 @@
+// Internal definitions shared by the HIP kernels and the host driver of
+// libbmr: the device-resident solver state, workspace layout and the launch
+// wrappers.  Not part of the public ABI (see include/bmr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bmr.h"
+
+namespace bmr {
+
+constexpr int MAXP = BMR_MAX_P;
+constexpr int MAXB = BMR_MAX_BENCH;
+constexpr int STATUS_RUNNING = 100;
+
+// Why the device loop stopped (DevState::reason).
+enum : int {
+  REASON_NONE = 0,
+  REASON_FINISHED = 1,     // converged, max_iter or bench exhausted
+  REASON_EXPLICIT_QR = 2,  // the Gram QR of the new block was rejected; host runs it column-wise
+  REASON_ERROR = 3,
+};
+
+// Number of reduced entries pass 1 produces for block size p and bench nb:
+// G = V_k^T W (p x p), Q = W^T W (p x p), P = V_k^T V_k (p x p),
+// a = column norms^2 of A V_k (p), W^T g (p x nb), V_k^T g (p x nb), g^T g (nb x nb).
+__host__ __device__ constexpr int n_entries(int p, int nb) { return 3 * p * p + p + 2 * p * nb + nb * nb; }
+__host__ __device__ constexpr int off_G(int) { return 0; }
+__host__ __device__ constexpr int off_Q(int p) { return p * p; }
+__host__ __device__ constexpr int off_P(int p) { return 2 * p * p; }
+__host__ __device__ constexpr int off_a(int p) { return 3 * p * p; }
+__host__ __device__ constexpr int off_Wg(int p) { return 3 * p * p + p; }
+__host__ __device__ constexpr int off_Vg(int p, int nb) { return 3 * p * p + p + p * nb; }
+__host__ __device__ constexpr int off_gg(int p, int nb) { return 3 * p * p + p + 2 * p * nb; }
+
+// Device-resident state of one solve.  Written by the host once, then only by
+// the single-workgroup band kernel (and by the host while the device loop is
+// halted for a column-wise QR).  Small matrices use a fixed stride MAXP:
+// M[r * MAXP + c] is row r, column c (0-based).
+struct DevState {
+  // ---- control --------------------------------------------------------
+  int halt;          // != 0: pass 1, the reduction and the band kernel return at once
+  int status;        // bmr_status once finished, STATUS_RUNNING before
+  int reason;        // REASON_*
+  int taken;         // bench vectors consumed
+  int64_t k;         // block iteration the next pass 1 works on (1-based)
+  int64_t k2;        // block iteration pass 2 applies (0: pass 2 does nothing)
+  int64_t j;         // band iterations completed
+  int lstar;         // columns of block k2 whose search direction enters X
+  int n_replaced;
+  int n_explicit;
+  int lcap;          // the band kernel processes columns l < lcap of the block (p normally)
+  int cap_status;    // status to finish with when it reaches lcap < p
+  int _pad0;
+  // ---- parameters -------------------------------------------------------
+  int p, nb;
+  int64_t n;
+  int64_t max_iter;
+  int64_t hist_cap;
+  double tol, gamma, tau_fb;
+  double beta[MAXP];          // ||b_i||
+  double bench_norm0[MAXB];   // initial norms of the bench vectors
+  // ---- band state ------------------------------------------------------
+  double Bprev[MAXP * MAXP];  // B_{k-1}: h_{(k-1)p+r+1, (k-2)p+c+1}, upper triangular
+  double Ak[MAXP * MAXP];     // A_k: diagonal block of H-bar, symmetric
+  double Bk[MAXP * MAXP];     // B_k: upper triangular, diagonal = h_{j+p,j}
+  double rot[3][MAXP][MAXP][2];  // Givens (c, s) of the columns of block b, ring b mod 3
+  double Shat[MAXP * MAXP];   // live rows of S-hat at the start of block k
+  // ---- coefficients for pass 2 of block k2 ------------------------------
+  double P2A[MAXP * MAXP];    // W' = W - V_k * P2A
+  double P2B[MAXP * MAXP];    // V_{k+1} = W' * P2B^{-1} (upper triangular)
+  double Ra[MAXP * MAXP];     // R rows of block k-2 (lower part), columns of block k
+  double Rb[MAXP * MAXP];     // R rows of block k-1
+  double Rc[MAXP * MAXP];     // R rows of block k (upper triangular)
+  double Z[MAXP * MAXP];      // row l = z_j^T for j = (k-1)p + l + 1
+  double bcoef[MAXB * MAXP];  // bench update: g_b -= V_{k+1} bcoef[b]
+  double araw[MAXP];          // ||A u_j|| of the block's columns
+  double rho[MAXP];           // last rho_j / beta
+};
+
+// Workspace carve-up (device pointers into the caller's workspace).
+struct Layout {
+  size_t off_state, off_red, off_part, off_hist, off_V, off_M, off_bench, total;
+  int n_wg;  // workgroups of pass 1 (partials)
+};
+
+Layout layout_for(int64_t n, int p, int nb, int64_t hist_cap);
+int pass1_grid(int64_t n, int p);
+
+// ---- launch wrappers (kernels_*.hip) ------------------------------------
+hipError_t launch_pass1(int p, const bmr_csr_t& A, double* Vbase, size_t slot_elems, double* bench,
+                        double* part, int n_wg, DevState* st, hipStream_t s);
+hipError_t launch_spmm(int p, const bmr_csr_t& A, const double* V, double* W, hipStream_t s);
+hipError_t launch_residual(int p, const bmr_csr_t& A, const double* B, const double* X, double* R,
+                           double* part, int n_wg, hipStream_t s);
+hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, DevState* st, int check_halt,
+                         hipStream_t s);
+hipError_t launch_band(int mode, const double* red, double* hist, DevState* st, hipStream_t s);
+hipError_t launch_pass2(int p, double* Vbase, double* Mbase, size_t slot_elems, double* X, double* bench,
+                        int64_t n, DevState* st, hipStream_t s);
+hipError_t launch_fill(double* x, size_t count, double v, hipStream_t s);
+hipError_t launch_bench_init(double* bench, int64_t n, int nb, uint64_t seed, hipStream_t s);
+// Column kernels of the column-wise (explicit) QR path.
+//   coldots: part[wg * (m+1) + r] = sum_i X[i*ldx + r] * Y[i*ldy + yc] (r < m), last = sum Y^2
+hipError_t launch_coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m, int64_t n,
+                          double* part, int n_wg, hipStream_t s);
+struct ColCoef { double c[MAXP]; };
+//   colop: D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef.c[r] * X[i*ldx + r]) / div
+hipError_t launch_colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx,
+                        int m, ColCoef coef, double div, int64_t n, hipStream_t s);
+int coldots_grid(int64_t n);
+
+}  // namespace bmr

@@ -1,0 +1,255 @@
+// Row-streaming kernels of a block iteration and the column kernels of the
+// column-wise QR path.
+//
+// Pass 2 touches every row once and keeps each row's p values in registers
+// (one lane per row): it finishes the orthogonalisation of the candidates,
+//     W' = W - V_k A_k,  V_{k+1} = W' B_k^{-1}          (forward substitution),
+// updates the substitute bench against V_{k+1} (Section 5.1), forms the
+// search directions of the block (eq. (4.1)),
+//     M_k = (V_k - M_{k-2} R_a - M_{k-1} R_b) R_c^{-1},
+// and adds them to the iterate (eq. (4.2)), X += M_k(:, 1:l*) Z_k(1:l*, :).
+// Every per-row operation runs in the order of the one-vector-per-iteration
+// algorithm, so that only the inner products differ in rounding.
+// The p x p coefficient blocks come from the band kernel through the device
+// state and are staged in LDS once per workgroup.
+#include "bmr_internal.hpp"
+
+namespace bmr {
+namespace {
+
+constexpr int WG = 256;
+
+template <int P>
+__global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double* __restrict__ Mbase, size_t slot,
+                                              double* __restrict__ X, double* __restrict__ bench, int64_t n,
+                                              const DevState* __restrict__ st) {
+  const int64_t k = st->k2;
+  if (k == 0) return;
+  __shared__ double sA[P * P], sB[P * P], sRa[P * P], sRb[P * P], sRc[P * P], sZ[P * P], sBc[MAXB * P];
+  for (int e = threadIdx.x; e < P * P; e += WG) {
+    const int r = e / P, c = e % P, o = r * MAXP + c;
+    sA[e] = st->P2A[o];
+    sB[e] = st->P2B[o];
+    sRa[e] = st->Ra[o];
+    sRb[e] = st->Rb[o];
+    sRc[e] = st->Rc[o];
+    sZ[e] = st->Z[o];
+  }
+  for (int e = threadIdx.x; e < MAXB * P; e += WG) sBc[e] = st->bcoef[(e / P) * MAXP + (e % P)];
+  __syncthreads();
+  const int lstar = st->lstar, nb = st->nb, taken = st->taken;
+  const double* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
+  double* __restrict__ Wn = Vbase + (size_t)((k + 1) % 3) * slot;
+  const double* __restrict__ Mm2 = Mbase + (size_t)((k + 1) % 3) * slot;  // M_{k-2}
+  const double* __restrict__ Mm1 = Mbase + (size_t)((k + 2) % 3) * slot;  // M_{k-1}
+  double* __restrict__ Mk = Mbase + (size_t)(k % 3) * slot;
+
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
+    double v[P], w[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      v[c] = V[row * P + c];
+      w[c] = Wn[row * P + c];
+    }
+    // finish the band orthogonalisation: column l loses sum_r A_k(r, l) u_r,
+    // then the earlier new vectors of its own block
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+#pragma unroll
+      for (int r = 0; r < P; ++r) w[l] = fma(-v[r], sA[r * P + l], w[l]);
+    }
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+#pragma unroll
+      for (int r = 0; r < l; ++r) w[l] = fma(-w[r], sB[r * P + l], w[l]);
+      w[l] = w[l] / sB[l * P + l];
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) Wn[row * P + c] = w[c];
+    // keep the unused substitutes orthogonal to the new basis vectors
+    for (int b = taken; b < nb; ++b) {
+      double g = bench[row * nb + b];
+#pragma unroll
+      for (int l = 0; l < P; ++l) g = fma(-w[l], sBc[b * P + l], g);
+      bench[row * nb + b] = g;
+    }
+    // search directions of the block
+    double m2[P], m1[P], mk[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      m2[c] = Mm2[row * P + c];
+      m1[c] = Mm1[row * P + c];
+      mk[c] = 0.0;
+    }
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      if (l < lstar) {
+        double m = v[l];
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+          if (r >= l) m = fma(-sRa[r * P + l], m2[r], m);
+#pragma unroll
+        for (int r = 0; r < P; ++r) m = fma(-sRb[r * P + l], m1[r], m);
+#pragma unroll
+        for (int r = 0; r < l; ++r) m = fma(-sRc[r * P + l], mk[r], m);
+        mk[l] = m / sRc[l * P + l];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) Mk[row * P + c] = mk[c];
+    // progressive update of the iterate
+    double x[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) x[c] = X[row * P + c];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
+      if (l < lstar) {
+#pragma unroll
+        for (int c = 0; c < P; ++c) x[c] = fma(mk[l], sZ[l * P + c], x[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) X[row * P + c] = x[c];
+  }
+}
+
+__global__ void k_fill(double* __restrict__ x, size_t count, double v) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) x[i] = v;
+}
+
+// SplitMix64 (S. Vigna's public-domain reference): the (c+1)-th output of the
+// stream seeded with `seed` is mix(seed + (c+1) * golden).  Entry i of bench
+// vector b uses counter c = b*n + i; the top 53 bits map to [-1, 1).
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_bench_init(double* __restrict__ bench, int64_t n, int nb, uint64_t seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    for (int b = 0; b < nb; ++b) {
+      const uint64_t bits = splitmix64_at(seed, (uint64_t)b * (uint64_t)n + (uint64_t)i) >> 11;
+      bench[i * nb + b] = 2.0 * ((double)bits * 0x1.0p-53) - 1.0;
+    }
+}
+
+// part[wg*(m+1) + r] = sum_i X[i*ldx + r] * Y[i*ldy + yc] (r < m); part[wg*(m+1) + m] = sum_i Y^2
+__global__ __launch_bounds__(WG) void k_coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m,
+                                                int64_t n, double* __restrict__ part) {
+  double acc[MAXP + 1];
+#pragma unroll
+  for (int r = 0; r <= MAXP; ++r) acc[r] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+    const double y = Y[i * ldy + yc];
+#pragma unroll
+    for (int r = 0; r < MAXP; ++r)
+      if (r < m) acc[r] = fma(X[i * ldx + r], y, acc[r]);
+    acc[MAXP] = fma(y, y, acc[MAXP]);
+  }
+  __shared__ double sh[WG];
+  for (int r = 0; r <= m; ++r) {
+    const double a = (r < m) ? acc[r] : acc[MAXP];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (m + 1) + r] = sh[0];
+    __syncthreads();
+  }
+}
+
+// D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef[r] * X[i*ldx + r]) / div
+// D may be the same column as S (in place) and X may be other columns of the
+// same block, so none of the pointers is restrict-qualified.
+__global__ void k_colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx, int m,
+                        ColCoef coef, double div, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double y = S[i * lds + sc];
+    for (int r = 0; r < m; ++r) y = fma(-coef.c[r], X[i * ldx + r], y);
+    D[i * ldd + dc] = y / div;
+  }
+}
+
+}  // namespace
+
+int coldots_grid(int64_t n) {
+  int64_t g = (n + WG - 1) / WG;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+static int stream_grid(int64_t n) {
+  int64_t g = (n + WG - 1) / WG;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+#define BMR_DISPATCH_P(p, MACRO) \
+  switch (p) {                   \
+    case 1: MACRO(1); break;     \
+    case 2: MACRO(2); break;     \
+    case 3: MACRO(3); break;     \
+    case 4: MACRO(4); break;     \
+    case 5: MACRO(5); break;     \
+    case 6: MACRO(6); break;     \
+    case 7: MACRO(7); break;     \
+    case 8: MACRO(8); break;     \
+    case 9: MACRO(9); break;     \
+    case 10: MACRO(10); break;   \
+    case 11: MACRO(11); break;   \
+    case 12: MACRO(12); break;   \
+    case 13: MACRO(13); break;   \
+    case 14: MACRO(14); break;   \
+    case 15: MACRO(15); break;   \
+    case 16: MACRO(16); break;   \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_pass2(int p, double* Vbase, double* Mbase, size_t slot, double* X, double* bench, int64_t n,
+                        DevState* st, hipStream_t s) {
+  const int g = stream_grid(n);
+#define L4(P) hipLaunchKernelGGL(k_pass2<P>, dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, bench, n, st)
+  BMR_DISPATCH_P(p, L4)
+#undef L4
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* x, size_t count, double v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  size_t g = (count + WG - 1) / WG;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(WG), 0, s, x, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_bench_init(double* bench, int64_t n, int nb, uint64_t seed, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bench_init, dim3(stream_grid(n)), dim3(WG), 0, s, bench, n, nb, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m, int64_t n, double* part,
+                          int n_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldots, dim3(n_wg), dim3(WG), 0, s, Y, ldy, yc, X, ldx, m, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx, int m,
+                        ColCoef coef, double div, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_colop, dim3(stream_grid(n)), dim3(WG), 0, s, D, ldd, dc, S, lds, sc, X, ldx, m, coef, div,
+                     n);
+  return hipGetLastError();
+}
+
+}  // namespace bmr

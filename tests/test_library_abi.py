@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every symbol include/bmr.h declares;
+host-side argument checks and workspace sizing work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1301_2102_amd as bmr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bmr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bmr_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(bmr.LIB_PATH):
+        pytest.fail("libbmr.so is not built (python -m paper_1301_2102_amd.build)")
+    return bmr.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(names) == set(bmr.EXPORTS)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings(lib):
+    assert lib.bmr_version() == 10000
+    for code, word in [(0, "converged"), (1, "maximum"), (2, "bench"), (-1, "invalid"), (-2, "workspace"),
+                       (-3, "HIP"), (-4, "non-finite"), (-5, "singular")]:
+        assert word in bmr.status_string(code)
+
+
+def test_default_opts(lib):
+    o = bmr._Opts()
+    lib.bmr_default_opts(ctypes.byref(o))
+    assert (o.tol, o.max_iter, o.gamma, o.n_bench, o.seed, o.hist_cap, o.flags) == (1e-8, 10000, 1e-10, 2, 0, 0, 0)
+
+
+def test_workspace_bytes(lib):
+    n, p = 2097152, 8
+    ws = bmr.workspace_bytes(n, p)
+    blocks = 6 * n * p * 8 + 2 * n * 8  # V and M rings + bench
+    assert blocks < ws < blocks + (16 << 20)
+    assert bmr.workspace_bytes(n, p, hist_cap=1000) >= ws + 1000 * p * 8
+    out = ctypes.c_size_t()
+    for bad in [(0, 8), (10, 0), (10, 17)]:
+        assert lib.bmr_workspace_bytes(bad[0], bad[1], None, ctypes.byref(out)) == bmr.INVALID_ARG
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    A = bmr._Csr(10, 28, 1, 1, 1)
+    o = bmr._Opts()
+    lib.bmr_default_opts(ctypes.byref(o))
+    st = bmr._Stats()
+    # null B / X / workspace, bad p, bad tol: rejected before any device work
+    assert lib.bmr_solve(ctypes.byref(A), None, 1, 4, ctypes.byref(o), 256, 1 << 20, None, ctypes.byref(st),
+                         None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 0, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 17, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    o.tol = 0.0
+    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    lib.bmr_default_opts(ctypes.byref(o))
+    o.n_bench = 5
+    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    lib.bmr_default_opts(ctypes.byref(o))
+    # unaligned and too small workspaces
+    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 257, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 256, 16, None, None,
+                         None) == bmr.WORKSPACE_TOO_SMALL
+    assert lib.bmr_spmm(ctypes.byref(A), 1, 1, 0, None) == bmr.INVALID_ARG
+    assert lib.bmr_spmm(ctypes.byref(A), 1, 1, 4, None) == bmr.INVALID_ARG  # V aliases W
+    bad = bmr._Csr(0, 0, 1, 1, 1)
+    assert lib.bmr_spmm(ctypes.byref(bad), 1, 2, 4, None) == bmr.INVALID_ARG
+
+
+def test_no_cpu_fallback_in_product_path():
+    """The package never imports the oracle: the product path has no CPU route."""
+    pkg = os.path.join(ROOT, "paper_1301_2102_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
