@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=32)
     ap.add_argument("--spmm-reps", type=int, default=50)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -159,25 +161,42 @@ def main():
                    "GB/s": round(nbytes[k] / (km[k] * 1e-3) / 1e9, 1) if k in nbytes else None}
                for k in ("pass1_spmm_gram", "reduce", "band", "pass2_update")}
 
-    # standalone block operator W = A V, p = 1, 8, 16 (same matrix)
+    # standalone block operator W = A V, p = 1, 8, 16 (same matrix).  The
+    # launches are captured in a graph so that the host's per-call cost does
+    # not pace the GPU; HIP events bracket the replay on the same stream.
     spmm = {}
     for q in (1, 8, 16):
         V = torch.from_numpy(rhs_normal(n, q, seed=1)).to(dev)
         W = torch.empty_like(V)
         for _ in range(3):
             bmr.spmm(Ad, V, W)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(args.spmm_reps):
+                bmr.spmm(Ad, V, W)
+        graph.replay()
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(args.spmm_reps):
-            bmr.spmm(Ad, V, W)
+        graph.replay()
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.spmm_reps
+        del graph
         b = kernel_bytes(A, q, 0)["spmm"]
         spmm[f"p{q}"] = {"avg_ms": round(ms, 5), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
                          "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": b}
         del V, W
     log(f"[bench] spmm: {spmm}")
+
+    if args.copy_ref_mib:
+        src = torch.empty(args.copy_ref_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

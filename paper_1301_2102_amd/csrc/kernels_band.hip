@@ -1,4 +1,4 @@
-// Reduction of the pass-1 partial sums and the band kernel: one workgroup
+// Reduction of the pass-1 partial sums and the band kernel: one wavefront
 // that turns the p x p Gram products of a block iteration into the new block
 // of the band Hessenberg matrix, reduces its p columns by Givens rotations,
 // updates the rotated right-hand-side window S-hat, records the residual
@@ -18,9 +18,19 @@
 // products of pass 1.  When a pivot falls below tau * ||A u_j|| the Gram
 // route cannot resolve the dependence test (Section 5) and the host runs the
 // new-block QR column by column instead.
+//
+// Work split inside the wavefront: lane l owns column l of the block (its
+// 4p band entries, kept in LDS) and column l of the S-hat window.  The
+// rotations of the two previous blocks are applied by all lanes at once; the
+// rotations of the block itself are generated column after column by the
+// owning lane and applied by the lanes to its right.  Floating-point
+// contraction is off so that every scalar step rounds like the plain
+// one-vector-per-iteration formulation.
 #include <math.h>
 
 #include "bmr_internal.hpp"
+
+#pragma clang fp contract(off)
 
 namespace bmr {
 namespace {
@@ -43,16 +53,23 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
 }
 
 // Givens pair zeroing b against a: r = hypot(a, b), c = a / r, s = b / r;
-// the identity when b is exactly zero.
-__device__ inline void givens(double a, double b, double& c, double& s) {
+// the identity (r = a) when b is exactly zero.  Returns r.
+__device__ inline double givens(double a, double b, double& c, double& s) {
   if (b == 0.0) {
     c = 1.0;
     s = 0.0;
-  } else {
-    const double r = hypot(a, b);
-    c = a / r;
-    s = b / r;
+    return a;
   }
+  const double r = hypot(a, b);
+  c = a / r;
+  s = b / r;
+  return r;
+}
+
+__device__ inline void rotate(double c, double s, double& x, double& y) {
+  const double a = x, b = y;
+  x = c * a + s * b;
+  y = -s * a + c * b;
 }
 
 __device__ void halt_with(DevState* st, int status, int reason) {
@@ -62,243 +79,353 @@ __device__ void halt_with(DevState* st, int status, int reason) {
   st->k2 = 0;
 }
 
-// Phase A: A_k, Gram of the remainder, Cholesky -> B_k and bench coefficients.
-// Returns false when the column-wise QR must take over.
-__device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ st) {
-#pragma clang fp contract(off)
-  const int p = st->p, nb = st->nb, taken = st->taken;
-  const double* G = red + off_G(p);
-  const double* Q = red + off_Q(p);
-  const double* Pm = red + off_P(p);
-  const double* a2 = red + off_a(p);
-  const double* Wg = red + off_Wg(p);
-  const double* Vg = red + off_Vg(p, nb);
-  double* Ak = st->Ak;
-  double* Bk = st->Bk;
-  for (int r = 0; r < p; ++r)
-    for (int c = 0; c < p; ++c) Ak[r * MAXP + c] = (r >= c) ? G[r * p + c] : G[c * p + r];
-  for (int c = 0; c < p; ++c) st->araw[c] = sqrt(a2[c]);
-  // Gamma = Q - Ak^T G - G^T Ak + Ak^T Pm Ak   (Gram of W - V_k A_k)
-  double T1[MAXP * MAXP], T2[MAXP * MAXP], Gam[MAXP * MAXP];
-  for (int l = 0; l < p; ++l)
-    for (int m = 0; m < p; ++m) {
-      double t = 0.0, u = 0.0;
-      for (int r = 0; r < p; ++r) {
-        t += Ak[r * MAXP + l] * G[r * p + m];
-        u += Pm[l * p + r] * Ak[r * MAXP + m];
-      }
-      T1[l * MAXP + m] = t;  // (Ak^T G)(l, m)
-      T2[l * MAXP + m] = u;  // (Pm Ak)(l, m)
-    }
-  for (int l = 0; l < p; ++l)
-    for (int m = 0; m < p; ++m) {
-      double t = 0.0;
-      for (int r = 0; r < p; ++r) t += Ak[r * MAXP + l] * T2[r * MAXP + m];
-      Gam[l * MAXP + m] = Q[l * p + m] - T1[l * MAXP + m] - T1[m * MAXP + l] + t;
-    }
-  // Cholesky, row-oriented like the column-by-column Gram-Schmidt it replaces
-  for (int c = 0; c < MAXP * MAXP; ++c) Bk[c] = 0.0;
-  for (int l = 0; l < p; ++l) {
-    for (int r = 0; r < l; ++r) {
-      double t = 0.5 * (Gam[r * MAXP + l] + Gam[l * MAXP + r]);
-      for (int q = 0; q < r; ++q) t -= Bk[q * MAXP + r] * Bk[q * MAXP + l];
-      Bk[r * MAXP + l] = t / Bk[r * MAXP + r];
-    }
-    double d = Gam[l * MAXP + l];
-    for (int q = 0; q < l; ++q) d -= Bk[q * MAXP + l] * Bk[q * MAXP + l];
-    const double thr = st->tau_fb * st->araw[l];
-    if (!(d > 0.0) || !(sqrt(d) >= thr) || !isfinite(d)) return false;
-    Bk[l * MAXP + l] = sqrt(d);
+template <int P>
+struct BandShared {
+  double Ak[P][P], Bk[P][P], Bp[P][P];
+  double G[P * P], Q[P * P], Pm[P * P];
+  double T1[P][P], T2[P][P], Gam[P][P];
+  double araw[P], beta[P];
+  double rot[2][P][P][2];  // rotations of blocks k-2 and k-1
+  double nrot[P][P][2];    // rotations of block k
+  double col[P][4 * P + 1];  // column l of H-bar, rows of blocks k-2 .. k+1
+  double s2[P][2 * P + 1];   // column q of the S-hat window (p live + p new rows)
+  double piv;
+  int flag;
+};
+
+// Phase A: A_k, Gram of the remainder, Cholesky -> B_k, bench coefficients.
+// Returns false (the same in every lane) when the column-wise QR must take
+// over.  Leaves A_k and B_k in shared memory.
+template <int P>
+__device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ st, BandShared<P>& sh) {
+  const int tid = threadIdx.x;
+  const int nb = st->nb, taken = st->taken;
+  for (int e = tid; e < P * P; e += 64) {
+    sh.G[e] = red[off_G(P) + e];
+    sh.Q[e] = red[off_Q(P) + e];
+    sh.Pm[e] = red[off_P(P) + e];
   }
-  // bench: coefficients of V_{k+1}^T g_b = B_k^{-T} (W^T g_b - A_k^T V_k^T g_b)
-  for (int b = 0; b < MAXB; ++b)
-    for (int l = 0; l < MAXP; ++l) st->bcoef[b * MAXP + l] = 0.0;
-  for (int b = taken; b < nb; ++b) {
-    double cf[MAXP];
-    for (int l = 0; l < p; ++l) {
+  if (tid < P) sh.araw[tid] = sqrt(red[off_a(P) + tid]);
+  __syncthreads();
+  for (int e = tid; e < P * P; e += 64) {
+    const int r = e / P, c = e % P;
+    sh.Ak[r][c] = (r >= c) ? sh.G[r * P + c] : sh.G[c * P + r];
+  }
+  __syncthreads();
+  for (int e = tid; e < P * P; e += 64) {
+    const int l = e / P, m = e % P;
+    double t = 0.0, u = 0.0;
+    for (int r = 0; r < P; ++r) {
+      t += sh.Ak[r][l] * sh.G[r * P + m];
+      u += sh.Pm[l * P + r] * sh.Ak[r][m];
+    }
+    sh.T1[l][m] = t;  // (A_k^T G)(l, m)
+    sh.T2[l][m] = u;  // (Pm A_k)(l, m)
+  }
+  __syncthreads();
+  // Gram of W - V_k A_k:  Q - A_k^T G - G^T A_k + A_k^T Pm A_k
+  for (int e = tid; e < P * P; e += 64) {
+    const int l = e / P, m = e % P;
+    double t = 0.0;
+    for (int r = 0; r < P; ++r) t += sh.Ak[r][l] * sh.T2[r][m];
+    sh.Gam[l][m] = sh.Q[l * P + m] - sh.T1[l][m] - sh.T1[m][l] + t;
+  }
+  __syncthreads();
+  // symmetric working copy in T2 (off-diagonal entries averaged)
+  for (int e = tid; e < P * P; e += 64) {
+    const int l = e / P, m = e % P;
+    sh.T2[l][m] = (l == m) ? sh.Gam[l][l] : 0.5 * (sh.Gam[l][m] + sh.Gam[m][l]);
+    sh.Bk[l][m] = 0.0;
+  }
+  __syncthreads();
+  // right-looking Cholesky T2 = B_k^T B_k; each entry sees its subtractions
+  // in the same order as the row-oriented recurrence
+#pragma unroll 1
+  for (int l = 0; l < P; ++l) {
+    if (tid == 0) {
+      const double d = sh.T2[l][l];
+      const double thr = st->tau_fb * sh.araw[l];
+      const bool ok = (d > 0.0) && isfinite(d) && (sqrt(d) >= thr);
+      sh.flag = ok;
+      sh.piv = ok ? sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    if (!sh.flag) return false;
+    if (tid == l) sh.Bk[l][l] = sh.piv;
+    if (tid > l && tid < P) sh.Bk[l][tid] = sh.T2[l][tid] / sh.piv;
+    __syncthreads();
+    for (int e = tid; e < P * P; e += 64) {
+      const int r = e / P, c = e % P;
+      if (r > l && c > l) sh.T2[r][c] -= sh.Bk[l][r] * sh.Bk[l][c];
+    }
+    __syncthreads();
+  }
+  // bench: V_{k+1}^T g_b = B_k^{-T} (W^T g_b - A_k^T V_k^T g_b), one lane per vector
+  for (int e = tid; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
+  __syncthreads();
+  if (tid >= taken && tid < nb) {
+    const int b = tid;
+    const double* Wg = red + off_Wg(P);
+    const double* Vg = red + off_Vg(P, nb);
+    double cf[P];
+#pragma unroll
+    for (int l = 0; l < P; ++l) {
       double gw = Wg[l * nb + b];
-      for (int r = 0; r < p; ++r) gw -= Ak[r * MAXP + l] * Vg[r * nb + b];
-      for (int r = 0; r < l; ++r) gw -= Bk[r * MAXP + l] * cf[r];
-      cf[l] = gw / Bk[l * MAXP + l];
+      for (int r = 0; r < P; ++r) gw -= sh.Ak[r][l] * Vg[r * nb + b];
+#pragma unroll
+      for (int r = 0; r < l; ++r) gw -= sh.Bk[r][l] * cf[r];
+      cf[l] = gw / sh.Bk[l][l];
       st->bcoef[b * MAXP + l] = cf[l];
     }
   }
-  for (int c = 0; c < MAXP * MAXP; ++c) {
-    st->P2A[c] = Ak[c];
-    st->P2B[c] = Bk[c];
+  for (int e = tid; e < P * P; e += 64) {
+    const int r = e / P, c = e % P;
+    st->Ak[r * MAXP + c] = sh.Ak[r][c];
+    st->Bk[r * MAXP + c] = sh.Bk[r][c];
+    st->P2A[r * MAXP + c] = sh.Ak[r][c];
+    st->P2B[r * MAXP + c] = sh.Bk[r][c];
   }
+  if (tid < P) st->araw[tid] = sh.araw[tid];
+  __syncthreads();
   return true;
+}
+
+// Inputs of phase B that phase A does not touch: B_{k-1}, the rotations of
+// blocks k-2 and k-1, the S-hat window and the column norms of B.  Issued
+// first so that their latency overlaps phase A.
+template <int P>
+__device__ void load_band_inputs(const DevState* __restrict__ st, BandShared<P>& sh) {
+  const int tid = threadIdx.x;
+  const int64_t k = st->k;
+  for (int e = tid; e < P * P; e += 64) {
+    const int r = e / P, c = e % P;
+    sh.Bp[r][c] = st->Bprev[r * MAXP + c];
+  }
+  for (int e = tid; e < 2 * P * P; e += 64) {
+    const int b = e / (P * P), i = (e / P) % P, t = e % P;
+    const int64_t kb = k - 2 + b;  // block whose rotations these are
+    const bool have = kb >= 1;
+    const int rb = have ? (int)(kb % 3) : 0;
+    sh.rot[b][i][t][0] = have ? st->rot[rb][i][t][0] : 1.0;
+    sh.rot[b][i][t][1] = have ? st->rot[rb][i][t][1] : 0.0;
+  }
+  for (int e = tid; e < 2 * P * P; e += 64) {  // S-hat window, column-major per lane
+    const int q = e / (2 * P), r = e % (2 * P);
+    sh.s2[q][r] = (r < P) ? st->Shat[r * MAXP + q] : 0.0;
+  }
+  if (tid < P) sh.beta[tid] = st->beta[tid];
 }
 
 // Phase B: Givens QR of the p new columns of H-bar, S-hat window, residuals,
 // stopping test, coefficients of the search directions and of the X update.
-__device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist) {
-#pragma clang fp contract(off)
-  const int p = st->p;
+// Columns live in LDS and the outer loops stay rolled: the kernel runs as a
+// single wavefront, so compact code matters more than register residency.
+template <int P>
+__device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, BandShared<P>& sh) {
+  const int tid = threadIdx.x;
   const int64_t k = st->k;
   const int64_t j0 = st->j;
-  const double* Bprev = st->Bprev;
-  const double* Ak = st->Ak;
-  const double* Bk = st->Bk;
-  double col[4 * MAXP];
-  double S2[2 * MAXP][MAXP];
-  double nrot[MAXP][MAXP][2];
-  for (int r = 0; r < p; ++r)
-    for (int c = 0; c < p; ++c) {
-      S2[r][c] = st->Shat[r * MAXP + c];
-      S2[p + r][c] = 0.0;
-    }
-  int lstar = p;
-  int finished = 0, status = STATUS_RUNNING;
-  for (int l = 0; l < p; ++l) {
-    if (l >= st->lcap) {  // the column-wise QR ran out of substitutes at column l
-      status = st->cap_status;
+  const int lcap = st->lcap, cap_status = st->cap_status;
+  const double tol = st->tol;
+  const int64_t max_iter = st->max_iter, hist_cap = st->hist_cap;
+  // column l of H-bar over the rows of blocks k-2 .. k+1
+  for (int e = tid; e < 4 * P * P; e += 64) {
+    const int l = e / (4 * P), r = e % (4 * P);
+    double v = 0.0;
+    if (r >= P && r < 2 * P) v = (r - P >= l) ? sh.Bp[l][r - P] : 0.0;
+    if (r >= 2 * P && r < 3 * P) v = sh.Ak[r - 2 * P][l];
+    if (r >= 3 * P) v = (r - 3 * P <= l) ? sh.Bk[r - 3 * P][l] : 0.0;
+    sh.col[l][r] = v;
+  }
+  __syncthreads();
+  // rotations of columns j-2p .. j-1 that lie in blocks k-2 (i >= l) and k-1
+  if (tid < P) {
+    const int l = tid;
+#pragma unroll 1
+    for (int b = 0; b < 2; ++b)
+#pragma unroll 1
+      for (int i = (b == 0 ? l : 0); i < P; ++i) {
+        const int base = b * P + i;
+        double x = sh.col[l][base], y[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) y[t] = sh.col[l][base + 1 + t];
+#pragma unroll
+        for (int t = 0; t < P; ++t) rotate(sh.rot[b][i][t][0], sh.rot[b][i][t][1], x, y[t]);
+        sh.col[l][base] = x;
+#pragma unroll
+        for (int t = 0; t < P; ++t) sh.col[l][base + 1 + t] = y[t];
+      }
+  }
+  __syncthreads();
+
+  int lstar = P, finished = 0, status = STATUS_RUNNING;
+#pragma unroll 1
+  for (int i = 0; i < P; ++i) {
+    if (i >= lcap) {  // the column-wise QR ran out of substitutes at column i
+      status = cap_status;
       finished = 1;
-      lstar = l;
+      lstar = i;
       break;
     }
-    const int64_t j = j0 + l + 1;
-    for (int r = 0; r < 4 * MAXP; ++r) col[r] = 0.0;
-    for (int r = l; r < p; ++r) col[p + r] = Bprev[l * MAXP + r];
-    for (int r = 0; r < p; ++r) col[2 * p + r] = Ak[r * MAXP + l];
-    for (int r = 0; r <= l; ++r) col[3 * p + r] = Bk[r * MAXP + l];
-    // rotations of columns j-2p .. j-1 (blocks k-2, k-1 and the first l of block k)
-    if (k - 2 >= 1) {
-      const int rb = (int)((k - 2) % 3);
-      for (int i = l; i < p; ++i)
-        for (int t = 1; t <= p; ++t) {
-          const double c = st->rot[rb][i][t - 1][0], s = st->rot[rb][i][t - 1][1];
-          const double a = col[i], b = col[i + t];
-          col[i] = c * a + s * b;
-          col[i + t] = -s * a + c * b;
-        }
-    }
-    if (k - 1 >= 1) {
-      const int rb = (int)((k - 1) % 3);
-      for (int i = 0; i < p; ++i)
-        for (int t = 1; t <= p; ++t) {
-          const double c = st->rot[rb][i][t - 1][0], s = st->rot[rb][i][t - 1][1];
-          const double a = col[p + i], b = col[p + i + t];
-          col[p + i] = c * a + s * b;
-          col[p + i + t] = -s * a + c * b;
-        }
-    }
-    for (int i = 0; i < l; ++i)
-      for (int t = 1; t <= p; ++t) {
-        const double c = nrot[i][t - 1][0], s = nrot[i][t - 1][1];
-        const double a = col[2 * p + i], b = col[2 * p + i + t];
-        col[2 * p + i] = c * a + s * b;
-        col[2 * p + i + t] = -s * a + c * b;
-      }
-    // new rotations: zero the p subdiagonal entries of column j
-    const int piv = 2 * p + l;
-    for (int t = 1; t <= p; ++t) {
-      double c, s;
-      givens(col[piv], col[piv + t], c, s);
-      nrot[l][t - 1][0] = c;
-      nrot[l][t - 1][1] = s;
-      if (s != 0.0) {
-        col[piv] = hypot(col[piv], col[piv + t]);
-        col[piv + t] = 0.0;
-        for (int q = 0; q < p; ++q) {
-          const double a = S2[l][q], b = S2[l + t][q];
-          S2[l][q] = c * a + s * b;
-          S2[l + t][q] = -s * a + c * b;
+    const int64_t j = j0 + i + 1;
+    const int piv = 2 * P + i;
+    if (tid == i) {  // new rotations zero the p subdiagonal entries of column j
+      double x = sh.col[i][piv], y[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) y[t] = sh.col[i][piv + 1 + t];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        double c, s;
+        const double r = givens(x, y[t], c, s);
+        sh.nrot[i][t][0] = c;
+        sh.nrot[i][t][1] = s;
+        if (s != 0.0) {
+          x = r;
+          y[t] = 0.0;
         }
       }
+      sh.col[i][piv] = x;
+      sh.piv = x;
     }
-    if (!(col[piv] != 0.0)) {
-      halt_with(st, isfinite(col[piv]) ? BMR_SINGULAR_R : BMR_NONFINITE, REASON_ERROR);
-      st->j = j - 1;
+    __syncthreads();
+    if (!(sh.piv != 0.0)) {
+      if (tid == 0) {
+        halt_with(st, isfinite(sh.piv) ? BMR_SINGULAR_R : BMR_NONFINITE, REASON_ERROR);
+        st->j = j - 1;
+      }
       return;
     }
-    for (int r = 0; r < p; ++r) {
-      st->Ra[r * MAXP + l] = (r >= l) ? col[r] : 0.0;
-      st->Rb[r * MAXP + l] = col[p + r];
-      st->Rc[r * MAXP + l] = (r <= l) ? col[2 * p + r] : 0.0;
-    }
-    for (int q = 0; q < p; ++q) st->Z[l * MAXP + q] = S2[l][q];
-    // recurrence residual rho_j^{(i)} = ||S-hat(j+1:j+p, i)|| (eq. (3.5))
-    double worst = 0.0;
-    int bad = 0;
-    for (int q = 0; q < p; ++q) {
+    double ratio = 0.0;
+    if (tid < P) {
+      const int q = tid;
+      // column j of R: rows of blocks k-2, k-1 and k (lane q writes row q of each)
+      st->Ra[q * MAXP + i] = (q >= i) ? sh.col[i][q] : 0.0;
+      st->Rb[q * MAXP + i] = sh.col[i][P + q];
+      st->Rc[q * MAXP + i] = (q <= i) ? sh.col[i][2 * P + q] : 0.0;
+      if (q > i) {  // later columns of the block receive the rotations of column i
+        double x = sh.col[q][piv], y[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) y[t] = sh.col[q][piv + 1 + t];
+#pragma unroll
+        for (int t = 0; t < P; ++t) rotate(sh.nrot[i][t][0], sh.nrot[i][t][1], x, y[t]);
+        sh.col[q][piv] = x;
+#pragma unroll
+        for (int t = 0; t < P; ++t) sh.col[q][piv + 1 + t] = y[t];
+      }
+      // S-hat rows i .. i+p of column q
+      double x = sh.s2[q][i], y[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) y[t] = sh.s2[q][i + 1 + t];
+#pragma unroll
+      for (int t = 0; t < P; ++t)
+        if (sh.nrot[i][t][1] != 0.0) rotate(sh.nrot[i][t][0], sh.nrot[i][t][1], x, y[t]);
+      sh.s2[q][i] = x;
+      // recurrence residual rho_j^{(q)} = ||S-hat(j+1:j+p, q)|| (eq. (3.5))
       double ss = 0.0;
-      for (int t = 1; t <= p; ++t) ss += S2[l + t][q] * S2[l + t][q];
-      const double rho = sqrt(ss);
-      const double ratio = st->beta[q] > 0.0 ? rho / st->beta[q] : 0.0;
-      if (!isfinite(ratio)) bad = 1;
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        sh.s2[q][i + 1 + t] = y[t];
+        ss += y[t] * y[t];
+      }
+      ratio = sh.beta[q] > 0.0 ? sqrt(ss) / sh.beta[q] : 0.0;
+      st->Z[i * MAXP + q] = x;
       st->rho[q] = ratio;
-      if (j <= st->hist_cap) hist[(j - 1) * p + q] = ratio;
-      worst = fmax(worst, ratio);
+      if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
     }
-    if (bad) {
-      halt_with(st, BMR_NONFINITE, REASON_ERROR);
-      st->j = j - 1;
+    // stopping test over the wavefront: max ratio, any non-finite value
+    double worst = ratio;
+    int bad = isfinite(ratio) ? 0 : 1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      worst = fmax(worst, __shfl_xor(worst, o, 64));
+      bad |= __shfl_xor(bad, o, 64);
+    }
+    const int f = bad ? 2 : (worst < tol) ? 1 : (j >= max_iter) ? 3 : 0;
+    if (f == 2) {
+      if (tid == 0) {
+        halt_with(st, BMR_NONFINITE, REASON_ERROR);
+        st->j = j - 1;
+      }
       return;
     }
-    if (worst < st->tol) {
-      status = BMR_CONVERGED;
+    if (f) {
+      status = (f == 1) ? BMR_CONVERGED : BMR_MAX_ITER;
       finished = 1;
-    } else if (j >= st->max_iter) {
-      status = BMR_MAX_ITER;
-      finished = 1;
-    }
-    if (finished) {
-      lstar = l + 1;
+      lstar = i + 1;
       break;
     }
+    __syncthreads();
   }
   if (finished && lstar == 0) {
-    halt_with(st, status, REASON_FINISHED);
+    if (tid == 0) halt_with(st, status, REASON_FINISHED);
     return;
   }
-  st->lstar = lstar;
-  st->k2 = k;
   if (finished) {
-    st->j = j0 + lstar;
-    st->status = status;
-    st->reason = REASON_FINISHED;
-    st->halt = 1;
+    if (tid == 0) {
+      st->lstar = lstar;
+      st->k2 = k;
+      st->j = j0 + lstar;
+      st->status = status;
+      st->reason = REASON_FINISHED;
+      st->halt = 1;
+    }
     return;
   }
   const int rk = (int)(k % 3);
-  for (int i = 0; i < p; ++i)
-    for (int t = 0; t < p; ++t) {
-      st->rot[rk][i][t][0] = nrot[i][t][0];
-      st->rot[rk][i][t][1] = nrot[i][t][1];
-    }
-  for (int c = 0; c < MAXP * MAXP; ++c) st->Bprev[c] = Bk[c];
-  for (int r = 0; r < p; ++r)
-    for (int c = 0; c < p; ++c) st->Shat[r * MAXP + c] = S2[p + r][c];
-  st->j = j0 + p;
-  st->k = k + 1;
+  for (int e = tid; e < P * P; e += 64) {
+    const int i = e / P, t = e % P;
+    st->rot[rk][i][t][0] = sh.nrot[i][t][0];
+    st->rot[rk][i][t][1] = sh.nrot[i][t][1];
+    st->Bprev[i * MAXP + t] = sh.Bk[i][t];
+    st->Shat[i * MAXP + t] = sh.s2[t][P + i];
+  }
+  if (tid == 0) {
+    st->lstar = P;
+    st->k2 = k;
+    st->j = j0 + P;
+    st->k = k + 1;
+  }
 }
 
 // mode 0: phase A then phase B.  mode 1: the host has supplied B_k (column-
 // wise QR) and already formed V_{k+1}; run phase B with pass 2 told to keep
 // V_{k+1} as it is.
+template <int P>
 __global__ __launch_bounds__(64) void k_band(int mode, const double* __restrict__ red, double* __restrict__ hist,
                                             DevState* __restrict__ st) {
-  if (threadIdx.x != 0) return;
-  if (st->halt) {
-    st->k2 = 0;
+  __shared__ BandShared<P> sh;
+  const int tid = threadIdx.x;
+  if (tid == 0) sh.flag = st->halt;
+  __syncthreads();
+  if (sh.flag) {
+    if (tid == 0) st->k2 = 0;
     return;
   }
+  __syncthreads();
+  load_band_inputs<P>(st, sh);
   if (mode == 0) {
-    if (!phase_a(red, st)) {
-      st->reason = REASON_EXPLICIT_QR;
-      st->halt = 1;
-      st->k2 = 0;
+    if (!phase_a<P>(red, st, sh)) {
+      if (tid == 0) {
+        for (int e = 0; e < P * P; ++e) st->Ak[(e / P) * MAXP + (e % P)] = sh.Ak[e / P][e % P];
+        for (int c = 0; c < P; ++c) st->araw[c] = sh.araw[c];
+        st->reason = REASON_EXPLICIT_QR;
+        st->halt = 1;
+        st->k2 = 0;
+      }
       return;
     }
   } else {
-    for (int c = 0; c < MAXP * MAXP; ++c) {
-      st->P2A[c] = 0.0;
-      st->P2B[c] = ((c / MAXP) == (c % MAXP)) ? 1.0 : 0.0;
+    for (int e = tid; e < P * P; e += 64) {
+      const int r = e / P, c = e % P;
+      sh.Ak[r][c] = st->Ak[r * MAXP + c];
+      sh.Bk[r][c] = st->Bk[r * MAXP + c];
+      st->P2A[r * MAXP + c] = 0.0;
+      st->P2B[r * MAXP + c] = (r == c) ? 1.0 : 0.0;
     }
-    for (int c = 0; c < MAXB * MAXP; ++c) st->bcoef[c] = 0.0;
+    for (int e = tid; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
+    __syncthreads();
   }
-  phase_b(st, hist);
+  phase_b<P>(st, hist, sh);
 }
 
 }  // namespace
@@ -309,8 +436,28 @@ hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, D
   return hipGetLastError();
 }
 
-hipError_t launch_band(int mode, const double* red, double* hist, DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_band, dim3(1), dim3(64), 0, s, mode, red, hist, st);
+hipError_t launch_band(int p, int mode, const double* red, double* hist, DevState* st, hipStream_t s) {
+#define LB(P) hipLaunchKernelGGL(k_band<P>, dim3(1), dim3(64), 0, s, mode, red, hist, st)
+  switch (p) {
+    case 1: LB(1); break;
+    case 2: LB(2); break;
+    case 3: LB(3); break;
+    case 4: LB(4); break;
+    case 5: LB(5); break;
+    case 6: LB(6); break;
+    case 7: LB(7); break;
+    case 8: LB(8); break;
+    case 9: LB(9); break;
+    case 10: LB(10); break;
+    case 11: LB(11); break;
+    case 12: LB(12); break;
+    case 13: LB(13); break;
+    case 14: LB(14); break;
+    case 15: LB(15); break;
+    case 16: LB(16); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef LB
   return hipGetLastError();
 }
 

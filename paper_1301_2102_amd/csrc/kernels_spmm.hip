@@ -6,49 +6,106 @@
 //
 // Layout: every n x p block is row-interleaved (element (i, c) at i*p + c), so
 // the p values one matrix entry multiplies are one contiguous 8p-byte segment.
-// A group of LPR = next_pow2(p) lanes owns one row: lane c holds column c.
-// The lanes of a group load up to LPR (column, value) pairs of the row at once
-// and pass them round with cross-lane shuffles, so each row of A is read once
-// for all p columns.  Workgroups get contiguous row ranges, and the logical
-// workgroup id is remapped so that each of the 8 XCDs (whose L2 caches are
-// private) walks one contiguous slab of rows: the stencil neighbours of a row
-// then sit in the same L2.
+// For p >= 3 a group of LPR lanes owns one row and lane c holds CPL adjacent
+// columns (CPL = 2 for even p >= 6, so that one 16-byte load per lane and
+// matrix entry covers the segment); the group loads up to LPR (column, value)
+// pairs of the row at once, passes them round with cross-lane shuffles and
+// issues all of the gathered loads before it consumes any.  Each row of A is
+// read once for all p columns.  For p <= 2 one lane owns a whole row.  These
+// shapes come from a sweep of lanes per row, columns per lane and grid size on
+// the 128^3 Laplacian.
+//
+// The p x p Gram products of pass 1 (V^T V, V^T W, W^T W) are accumulated on
+// the matrix cores: each wavefront stages its rows of [V_k  W] in LDS and feeds
+// them, four rows at a time, to V_MFMA_F64_16X16X4F64 as both operands, so the
+// 16 x 16 accumulator collects X^T X for X = [V_k W] (p <= 8) or one product
+// per accumulator (p > 8).  The accumulators stay in registers for the whole
+// row range of the workgroup.
+#include <algorithm>
+
 #include "bmr_internal.hpp"
 
 namespace bmr {
 namespace {
 
 constexpr int WG = 256;
+constexpr int PASS1_MAX_WG = 4096;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Row layout for block size p: one lane per row for p <= 2; otherwise a group
+// of lpr lanes per row with cpl adjacent columns per lane.
+__host__ __device__ constexpr int layout_cpl(int p) { return p <= 2 ? p : ((p % 2 == 0 && p >= 6) ? 2 : 1); }
+__host__ __device__ constexpr int layout_lpr(int p) {
+  return p <= 2 ? 1 : ((p + layout_cpl(p) - 1) / layout_cpl(p) <= 4 ? 4 : (p + layout_cpl(p) - 1) / layout_cpl(p) <= 8 ? 8 : 16);
+}
+__host__ __device__ constexpr int layout_rpg(int p) { return (WG / 64) * (64 / layout_lpr(p)); }
 
 template <int P>
 struct Lanes {
-  static constexpr int LPR = P <= 1 ? 1 : P <= 2 ? 2 : P <= 4 ? 4 : P <= 8 ? 8 : 16;
-  static constexpr int RPW = 64 / LPR;        // rows per wavefront
-  static constexpr int RPG = (WG / 64) * RPW; // rows per workgroup step
+  static constexpr bool ROW = P <= 2;                // one lane per row
+  static constexpr int CPL = layout_cpl(P);          // columns per lane
+  static constexpr int LPR = layout_lpr(P);          // lanes per row
+  static constexpr int RPW = 64 / LPR;               // rows per wavefront
+  static constexpr int RPG = layout_rpg(P);          // rows per workgroup step
 };
-
-__device__ inline int logical_wg(int n_wg) {
-  const int w = blockIdx.x;
-  return (w % 8) * (n_wg / 8) + (w / 8);
-}
 
 __device__ inline double shfl_d(double x, int src, int width) { return __shfl(x, src, width); }
 
-// acc = sum over the entries of `row` of val * V[col*P + c], in CSR order.
-// All LPR lanes of a group call this with the same row and `valid` flag.
-template <int P, int LPR>
-__device__ inline double gather_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                    const double* __restrict__ va, const double* __restrict__ V, int64_t row,
-                                    bool valid, int c) {
+// x[0..CPL) = V[off .. off + CPL) as one vector load
+template <int CPL>
+__device__ inline void vload(const double* __restrict__ p, double (&x)[CPL]) {
+  if constexpr (CPL == 2) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    x[0] = v.x;
+    x[1] = v.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) x[k] = p[k];
+  }
+}
+
+// acc[k] = sum over the entries of `row` of val * V[col*P + c0 + k], in CSR
+// order (c0 = c * CPL).  In the group layout all lanes of a group call this
+// with the same row; lanes whose columns lie beyond p return zeros.
+template <int P, int LPR, int CPL>
+__device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                  const double* __restrict__ va, const double* __restrict__ V, int64_t row,
+                                  bool valid, int c, double (&acc)[CPL]) {
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
   int s = 0, e = 0;
   if (valid) {
     s = rp[row];
     e = rp[row + 1];
   }
-  double acc = 0.0;
   if constexpr (LPR == 1) {
-    for (int q = s; q < e; ++q) acc = fma(va[q], V[(int64_t)ci[q] * P], acc);
+    constexpr int U = 8;
+    for (int q = s; q < e; q += U) {
+      int cq[U];
+      double vq[U], x[U][CPL];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool in = q + u < e;
+        cq[u] = in ? ci[q + u] : 0;
+        vq[u] = in ? va[q + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (q + u < e) {
+          vload<CPL>(V + (int64_t)cq[u] * P, x[u]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) x[u][k] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) acc[k] = fma(vq[u], x[u][k], acc[k]);
+    }
   } else {
+    constexpr int U = LPR < 8 ? LPR : 8;
+    const bool mine = c * CPL < P;
     for (int base = s; base < e; base += LPR) {
       const int idx = base + c;
       int col = 0;
@@ -58,14 +115,38 @@ __device__ inline double gather_row(const int32_t* __restrict__ rp, const int32_
         v = va[idx];
       }
       const int cnt = min(LPR, e - base);
-      for (int q = 0; q < cnt; ++q) {
-        const int cq = __shfl(col, q, LPR);
-        const double vq = shfl_d(v, q, LPR);
-        if (c < P) acc = fma(vq, V[(int64_t)cq * P + c], acc);
+      for (int q0 = 0; q0 < cnt; q0 += U) {
+        double co[U], x[U][CPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int cq = __shfl(col, q0 + u, LPR);
+          const double vq = shfl_d(v, q0 + u, LPR);
+          const bool in = q0 + u < cnt;
+          co[u] = in ? vq : 0.0;
+          if (in && mine) {
+            vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) x[u][k] = 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) acc[k] = fma(co[u], x[u][k], acc[k]);
       }
     }
   }
-  return acc;
+}
+
+// Contiguous row range [r0, r1) of logical workgroup L out of n_wg, in whole
+// workgroup steps of RPG rows.
+template <int RPG>
+__device__ inline void row_range(int64_t n, int n_wg, int L, int64_t& r0, int64_t& r1) {
+  const int64_t steps = (n + RPG - 1) / RPG;
+  const int64_t per = (steps + n_wg - 1) / n_wg;
+  r0 = (int64_t)L * per * RPG;
+  r1 = min(n, r0 + per * RPG);
 }
 
 // Sum x over the groups of a wavefront (lanes with equal c); the result is
@@ -83,119 +164,228 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
                                               size_t slot, const double* __restrict__ bench,
                                               double* __restrict__ part, int n_wg, DevState* __restrict__ st) {
   if (st->halt) return;
-  constexpr int LPR = Lanes<P>::LPR, RPW = Lanes<P>::RPW, RPG = Lanes<P>::RPG;
+  using LN = Lanes<P>;
+  constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int64_t k = st->k;
   const double* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
   const double* __restrict__ Vp = Vbase + (size_t)((k + 2) % 3) * slot;  // V_{k-1}
   double* __restrict__ W = Vbase + (size_t)((k + 1) % 3) * slot;         // becomes V_{k+1}
   const int nb = st->nb, taken = st->taken;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane / LPR, c = lane % LPR;
+  const int c0 = c * CPL;  // first column of this lane
 
-  double bp[P];  // row c of B_{k-1}
-#pragma unroll
-  for (int r = 0; r < P; ++r) bp[r] = (c < P) ? st->Bprev[c * MAXP + r] : 0.0;
+  __shared__ double sBp[P][P + 1];  // B_{k-1}, padded against bank conflicts
+  constexpr int SR = LN::ROW ? 1 : RPW;
+  __shared__ double sv[WG / 64][SR][16], sw[WG / 64][SR][16];  // staged rows of [V_k W]
+  for (int e = tid; e < P * P; e += WG) sBp[e / P][e % P] = st->Bprev[(e / P) * MAXP + (e % P)];
+  __syncthreads();
 
-  double aG[P], aQ[P], aP[P], aA = 0.0, aWg[MAXB], aVg[MAXB], aGg[MAXB * MAXB];
+  constexpr int NGG = (MAXB * MAXB + LPR - 1) / LPR;
+  double aA[CPL], aWg[CPL][MAXB], aVg[CPL][MAXB], aGg[NGG];
+  double lG[CPL][CPL], lQ[CPL][CPL], lP[CPL][CPL];  // one-lane-per-row Grams (p <= 2)
+  dbl4 m0 = {0, 0, 0, 0}, m1 = {0, 0, 0, 0}, m2 = {0, 0, 0, 0};  // matrix-core Grams
 #pragma unroll
-  for (int r = 0; r < P; ++r) aG[r] = aQ[r] = aP[r] = 0.0;
+  for (int cc = 0; cc < CPL; ++cc) {
+    aA[cc] = 0.0;
 #pragma unroll
-  for (int b = 0; b < MAXB; ++b) aWg[b] = aVg[b] = 0.0;
+    for (int b = 0; b < MAXB; ++b) aWg[cc][b] = aVg[cc][b] = 0.0;
 #pragma unroll
-  for (int b = 0; b < MAXB * MAXB; ++b) aGg[b] = 0.0;
+    for (int r = 0; r < CPL; ++r) lG[cc][r] = lQ[cc][r] = lP[cc][r] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NGG; ++q) aGg[q] = 0.0;
 
-  const int L = logical_wg(n_wg);
-  const int64_t chunk = ((n + n_wg - 1) / n_wg + RPG - 1) / RPG * RPG;
-  const int64_t r0 = (int64_t)L * chunk;
-  const int64_t r1 = min(n, r0 + chunk);
+  int64_t r0, r1;
+  row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
 
   for (int64_t base = r0; base < r1; base += RPG) {
+    asm volatile("" ::: "memory");
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
-    const double a = gather_row<P, LPR>(rp, ci, va, V, row, valid, c);
-    double v = 0.0, vp = 0.0;
-    if (valid && c < P) {
-      v = V[row * P + c];
-      vp = Vp[row * P + c];
-    }
-    // known coefficients by symmetry: column c loses sum_{r >= c} B_{k-1}(c, r) V_{k-1}(:, r)
-    double w = a;
+    double a[CPL];
+    gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
+    // this lane's values of V_k, and the whole row of V_{k-1}
+    double v[CPL], w[CPL], vp[P];
+    if (valid && c0 < P) {
+      vload<CPL>(V + row * P + c0, v);
+    } else {
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      const double vr = shfl_d(vp, r, LPR);
-      if (r >= c) w = fma(-bp[r], vr, w);
+      for (int cc = 0; cc < CPL; ++cc) v[cc] = 0.0;
     }
-    if (valid && c < P) W[row * P + c] = w;
-    aA = fma(a, a, aA);
+    if (valid) {
+      if constexpr (P % 2 == 0) {
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      const double vr = shfl_d(v, r, LPR);
-      const double wr = shfl_d(w, r, LPR);
-      aG[r] = fma(vr, w, aG[r]);
-      aQ[r] = fma(wr, w, aQ[r]);
-      aP[r] = fma(vr, v, aP[r]);
+        for (int r = 0; r < P; r += 2) {
+          const double2 t = *reinterpret_cast<const double2*>(Vp + row * P + r);
+          vp[r] = t.x;
+          vp[r + 1] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < P; ++r) vp[r] = Vp[row * P + r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < P; ++r) vp[r] = 0.0;
     }
+    // known coefficients by symmetry: column l loses sum_{r >= l} B_{k-1}(l, r) V_{k-1}(:, r)
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int col = c0 + cc;
+      double t = a[cc];
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+        if (r >= col && col < P) t = fma(-sBp[col][r], vp[r], t);
+      w[cc] = t;
+      aA[cc] = fma(a[cc], a[cc], aA[cc]);
+    }
+    if (valid && c0 < P) {
+      if constexpr (CPL == 2) {
+        *reinterpret_cast<double2*>(W + row * P + c0) = make_double2(w[0], w[1]);
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) W[row * P + c0 + cc] = w[cc];
+      }
+    }
+    // substitute bench: W^T g, V_k^T g, g^T g
     if (taken < nb) {
       double g[MAXB];
 #pragma unroll
       for (int b = 0; b < MAXB; ++b) g[b] = (b >= taken && b < nb && valid) ? bench[row * nb + b] : 0.0;
 #pragma unroll
-      for (int b = 0; b < MAXB; ++b) {
-        aWg[b] = fma(w, g[b], aWg[b]);
-        aVg[b] = fma(v, g[b], aVg[b]);
-      }
-      if (c == 0) {
+      for (int cc = 0; cc < CPL; ++cc)
 #pragma unroll
-        for (int b = 0; b < MAXB; ++b)
+        for (int b = 0; b < MAXB; ++b) {
+          aWg[cc][b] = fma(w[cc], g[b], aWg[cc][b]);
+          aVg[cc][b] = fma(v[cc], g[b], aVg[cc][b]);
+        }
 #pragma unroll
-          for (int b2 = 0; b2 < MAXB; ++b2) aGg[b * MAXB + b2] = fma(g[b], g[b2], aGg[b * MAXB + b2]);
+      for (int q = 0; q < NGG; ++q) {
+        const int e = c + q * LPR;  // entry (e / MAXB, e % MAXB) of g^T g
+        if (e < MAXB * MAXB) aGg[q] = fma(g[e / MAXB], g[e % MAXB], aGg[q]);
       }
+    }
+    // Gram products of the block
+    if constexpr (LN::ROW) {
+#pragma unroll
+      for (int r = 0; r < CPL; ++r)
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          lG[r][cc] = fma(v[r], w[cc], lG[r][cc]);
+          lQ[r][cc] = fma(w[r], w[cc], lQ[r][cc]);
+          lP[r][cc] = fma(v[r], v[cc], lP[r][cc]);
+        }
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        if (c0 + cc < 16) {
+          sv[wave][grp][c0 + cc] = v[cc];
+          sw[wave][grp][c0 + cc] = w[cc];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      const int m = lane % 16, rq = lane / 16;
+#pragma unroll
+      for (int h = 0; h < RPW / 4; ++h) {
+        const int rl = 4 * h + rq;
+        if constexpr (P <= 8) {
+          // X = [V_k | W] as 16 columns (zero padded), four rows per product
+          const double x = (m < 8) ? ((m < P) ? sv[wave][rl][m] : 0.0) : ((m - 8 < P) ? sw[wave][rl][m - 8] : 0.0);
+          m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, m0, 0, 0, 0);
+        } else {
+          const double xv = sv[wave][rl][m], xw = sw[wave][rl][m];
+          m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xv, m0, 0, 0, 0);  // V^T V
+          m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xw, m1, 0, 0, 0);  // V^T W
+          m2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xw, xw, m2, 0, 0, 0);  // W^T W
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
 
   // ---- workgroup reduction: deterministic order --------------------------
-  constexpr int NEMAX = n_entries(MAXP, MAXB);
-  __shared__ double sred[WG / 64][NEMAX];
+  constexpr int NEP = n_entries(P, MAXB);
+  __shared__ double sred[WG / 64][NEP];
   const int ne = n_entries(P, nb);
+  double* s = sred[wave];
+  for (int e = lane; e < ne; e += 64) s[e] = 0.0;
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int r = 0; r < P; ++r) {
-    aG[r] = group_sum<LPR>(aG[r]);
-    aQ[r] = group_sum<LPR>(aQ[r]);
-    aP[r] = group_sum<LPR>(aP[r]);
-  }
-  aA = group_sum<LPR>(aA);
-  if (taken < nb) {
+  for (int cc = 0; cc < CPL; ++cc) {
+    aA[cc] = group_sum<LPR>(aA[cc]);
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-      aWg[b] = group_sum<LPR>(aWg[b]);
-      aVg[b] = group_sum<LPR>(aVg[b]);
+      aWg[cc][b] = group_sum<LPR>(aWg[cc][b]);
+      aVg[cc][b] = group_sum<LPR>(aVg[cc][b]);
     }
-#pragma unroll
-    for (int b = 0; b < MAXB * MAXB; ++b) aGg[b] = group_sum<LPR>(aGg[b]);
   }
-  if (grp == 0 && c < P) {
-    double* s = sred[wave];
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      s[off_G(P) + r * P + c] = aG[r];
-      s[off_Q(P) + r * P + c] = aQ[r];
-      s[off_P(P) + r * P + c] = aP[r];
+  for (int q = 0; q < NGG; ++q) aGg[q] = group_sum<LPR>(aGg[q]);
+  if constexpr (LN::ROW) {
+#pragma unroll
+    for (int r = 0; r < CPL; ++r)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        lG[r][cc] = group_sum<1>(lG[r][cc]);
+        lQ[r][cc] = group_sum<1>(lQ[r][cc]);
+        lP[r][cc] = group_sum<1>(lP[r][cc]);
+      }
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < CPL; ++r)
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          s[off_G(P) + r * P + cc] = lG[r][cc];
+          s[off_Q(P) + r * P + cc] = lQ[r][cc];
+          s[off_P(P) + r * P + cc] = lP[r][cc];
+        }
     }
-    s[off_a(P) + c] = aA;
-    for (int b = 0; b < nb; ++b) {
-      s[off_Wg(P) + c * nb + b] = aWg[b];
-      s[off_Vg(P, nb) + c * nb + b] = aVg[b];
+  } else {
+    // accumulator layout (measured on gfx950): lane l, element i holds row
+    // 4*i + l/16, column l%16 of the 16 x 16 product
+    const int colD = lane % 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rowD = 4 * i + lane / 16;
+      if constexpr (P <= 8) {
+        const double d = m0[i];
+        if (rowD < P && colD < P) s[off_P(P) + rowD * P + colD] = d;
+        if (rowD < P && colD >= 8 && colD - 8 < P) s[off_G(P) + rowD * P + colD - 8] = d;
+        if (rowD >= 8 && rowD - 8 < P && colD >= 8 && colD - 8 < P) s[off_Q(P) + (rowD - 8) * P + colD - 8] = d;
+      } else {
+        if (rowD < P && colD < P) {
+          s[off_P(P) + rowD * P + colD] = m0[i];
+          s[off_G(P) + rowD * P + colD] = m1[i];
+          s[off_Q(P) + rowD * P + colD] = m2[i];
+        }
+      }
     }
-    if (c == 0)
-      for (int b = 0; b < nb; ++b)
-        for (int b2 = 0; b2 < nb; ++b2) s[off_gg(P, nb) + b * nb + b2] = aGg[b * MAXB + b2];
+  }
+  if (grp == 0) {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      const int col = c0 + cc;
+      if (col < P) {
+        s[off_a(P) + col] = aA[cc];
+        for (int b = 0; b < nb; ++b) {
+          s[off_Wg(P) + col * nb + b] = aWg[cc][b];
+          s[off_Vg(P, nb) + col * nb + b] = aVg[cc][b];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NGG; ++q) {
+      const int e = c + q * LPR, b = e / MAXB, b2 = e % MAXB;
+      if (e < MAXB * MAXB && b < nb && b2 < nb) s[off_gg(P, nb) + b * nb + b2] = aGg[q];
+    }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ne; e += WG) {
+  for (int e = tid; e < ne; e += WG) {
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < WG / 64; ++q) t += sred[q][e];
-    part[(size_t)e * n_wg + L] = t;
+    part[(size_t)e * n_wg + blockIdx.x] = t;
   }
 }
 
@@ -203,18 +393,25 @@ template <int P>
 __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const double* __restrict__ va, int64_t n, const double* __restrict__ V,
                                              double* __restrict__ W, int n_wg) {
-  constexpr int LPR = Lanes<P>::LPR, RPW = Lanes<P>::RPW, RPG = Lanes<P>::RPG;
+  using LN = Lanes<P>;
+  constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / LPR, c = lane % LPR;
-  const int L = logical_wg(n_wg);
-  const int64_t chunk = ((n + n_wg - 1) / n_wg + RPG - 1) / RPG * RPG;
-  const int64_t r0 = (int64_t)L * chunk;
-  const int64_t r1 = min(n, r0 + chunk);
+  const int grp = lane / LPR, c = lane % LPR, c0 = c * CPL;
+  int64_t r0, r1;
+  row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
   for (int64_t base = r0; base < r1; base += RPG) {
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
-    const double a = gather_row<P, LPR>(rp, ci, va, V, row, valid, c);
-    if (valid && c < P) W[row * P + c] = a;
+    double a[CPL];
+    gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
+    if (valid && c0 < P) {
+      if constexpr (CPL == 2) {
+        *reinterpret_cast<double2*>(W + row * P + c0) = make_double2(a[0], a[1]);
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) W[row * P + c0 + cc] = a[cc];
+      }
+    }
   }
 }
 
@@ -223,45 +420,56 @@ __global__ __launch_bounds__(WG) void k_residual(const int32_t* __restrict__ rp,
                                                  const double* __restrict__ va, int64_t n,
                                                  const double* __restrict__ Bm, const double* __restrict__ X,
                                                  double* __restrict__ R, double* __restrict__ part, int n_wg) {
-  constexpr int LPR = Lanes<P>::LPR, RPW = Lanes<P>::RPW, RPG = Lanes<P>::RPG;
+  using LN = Lanes<P>;
+  constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / LPR, c = lane % LPR;
-  const int L = logical_wg(n_wg);
-  const int64_t chunk = ((n + n_wg - 1) / n_wg + RPG - 1) / RPG * RPG;
-  const int64_t r0 = (int64_t)L * chunk;
-  const int64_t r1 = min(n, r0 + chunk);
-  double acc = 0.0;
+  const int grp = lane / LPR, c = lane % LPR, c0 = c * CPL;
+  int64_t r0, r1;
+  row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
+  double acc[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) acc[cc] = 0.0;
   for (int64_t base = r0; base < r1; base += RPG) {
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
-    const double ax = gather_row<P, LPR>(rp, ci, va, X, row, valid, c);
-    if (valid && c < P) {
-      const double r = Bm[row * P + c] - ax;
-      if (R) R[row * P + c] = r;
-      acc = fma(r, r, acc);
+    double ax[CPL];
+    gather_row<P, LPR, CPL>(rp, ci, va, X, row, valid, c, ax);
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      if (valid && c0 + cc < P) {
+        const double r = Bm[row * P + c0 + cc] - ax[cc];
+        if (R) R[row * P + c0 + cc] = r;
+        acc[cc] = fma(r, r, acc[cc]);
+      }
     }
   }
-  acc = group_sum<LPR>(acc);
-  __shared__ double s[WG / 64][LPR];
-  if (grp == 0) s[wave][c] = acc;
+  __shared__ double sh[WG / 64][16];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) {
+    acc[cc] = group_sum<LPR>(acc[cc]);
+    if (grp == 0 && c0 + cc < P) sh[wave][c0 + cc] = acc[cc];
+  }
   __syncthreads();
   if (threadIdx.x < P) {
     double t = 0.0;
-    for (int q = 0; q < WG / 64; ++q) t += s[q][threadIdx.x];
-    part[(size_t)threadIdx.x * n_wg + L] = t;
+    for (int q = 0; q < WG / 64; ++q) t += sh[q][threadIdx.x];
+    part[(size_t)threadIdx.x * n_wg + blockIdx.x] = t;
   }
 }
 
 }  // namespace
 
 int pass1_grid(int64_t n, int p) {
-  const int lpr = p <= 1 ? 1 : p <= 2 ? 2 : p <= 4 ? 4 : p <= 8 ? 8 : 16;
-  const int64_t rpg = (WG / 64) * (64 / lpr);
-  const int64_t steps = (n + rpg - 1) / rpg;
-  int64_t g = (steps + 3) / 4;  // at least ~4 steps per workgroup when large
-  if (g > 2048) g = 2048;
-  if (g < 8) g = 8;
-  return (int)((g + 7) / 8 * 8);
+  // one workgroup step of the row layout each, at most PASS1_MAX_WG
+  // workgroups so that the partial sums stay small
+  int64_t g = (n + layout_rpg(p) - 1) / layout_rpg(p);
+  if (g > PASS1_MAX_WG) g = PASS1_MAX_WG;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+static int spmm_grid(int64_t n, int p) {
+  return (int)std::max<int64_t>(1, (n + layout_rpg(p) - 1) / layout_rpg(p));  // one workgroup step each
 }
 
 #define BMR_DISPATCH_P(p, MACRO) \
@@ -296,7 +504,7 @@ hipError_t launch_pass1(int p, const bmr_csr_t& A, double* Vbase, size_t slot, d
 }
 
 hipError_t launch_spmm(int p, const bmr_csr_t& A, const double* V, double* W, hipStream_t s) {
-  const int n_wg = pass1_grid(A.n, p);
+  const int n_wg = spmm_grid(A.n, p);
 #define L2(P) hipLaunchKernelGGL(k_spmm<P>, dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, A.val, A.n, V, W, n_wg)
   BMR_DISPATCH_P(p, L2)
 #undef L2

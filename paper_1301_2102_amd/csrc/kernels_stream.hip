@@ -46,6 +46,9 @@ __global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double
 
   const int64_t stride = (int64_t)gridDim.x * WG;
   for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
+    // re-read the coefficients from LDS in every row rather than holding
+    // 6p^2 of them in registers for the whole loop
+    asm volatile("" ::: "memory");
     double v[P], w[P];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -74,30 +77,35 @@ __global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double
       for (int l = 0; l < P; ++l) g = fma(-w[l], sBc[b * P + l], g);
       bench[row * nb + b] = g;
     }
+    asm volatile("" ::: "memory");
     // search directions of the block
-    double m2[P], m1[P], mk[P];
+    double mk[P];
+    {
+      double m2[P], m1[P];
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-      m2[c] = Mm2[row * P + c];
-      m1[c] = Mm1[row * P + c];
-      mk[c] = 0.0;
-    }
+      for (int c = 0; c < P; ++c) {
+        m2[c] = Mm2[row * P + c];
+        m1[c] = Mm1[row * P + c];
+        mk[c] = 0.0;
+      }
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
-      if (l < lstar) {
-        double m = v[l];
+      for (int l = 0; l < P; ++l) {
+        if (l < lstar) {
+          double m = v[l];
 #pragma unroll
-        for (int r = 0; r < P; ++r)
-          if (r >= l) m = fma(-sRa[r * P + l], m2[r], m);
+          for (int r = 0; r < P; ++r)
+            if (r >= l) m = fma(-sRa[r * P + l], m2[r], m);
 #pragma unroll
-        for (int r = 0; r < P; ++r) m = fma(-sRb[r * P + l], m1[r], m);
+          for (int r = 0; r < P; ++r) m = fma(-sRb[r * P + l], m1[r], m);
 #pragma unroll
-        for (int r = 0; r < l; ++r) m = fma(-sRc[r * P + l], mk[r], m);
-        mk[l] = m / sRc[l * P + l];
+          for (int r = 0; r < l; ++r) m = fma(-sRc[r * P + l], mk[r], m);
+          mk[l] = m / sRc[l * P + l];
+        }
       }
     }
 #pragma unroll
     for (int c = 0; c < P; ++c) Mk[row * P + c] = mk[c];
+    asm volatile("" ::: "memory");
     // progressive update of the iterate
     double x[P];
 #pragma unroll

@@ -330,7 +330,7 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
       if (prof) HIP_TRY(hipEventRecord(pev[slot][1], r.s));
       HIP_TRY(launch_reduce(r.part, r.L.n_wg, n_entries(r.p, r.nb), r.red, r.st, 1, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][2], r.s));
-      HIP_TRY(launch_band(0, r.red, r.hist, r.st, r.s));
+      HIP_TRY(launch_band(r.p, 0, r.red, r.hist, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][3], r.s));
       HIP_TRY(launch_pass2(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][4], r.s));
@@ -380,7 +380,7 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
     hs->halt = 0;
     hs->reason = REASON_NONE;
     HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
-    HIP_TRY(launch_band(1, r.red, r.hist, r.st, r.s));
+    HIP_TRY(launch_band(r.p, 1, r.red, r.hist, r.st, r.s));
     HIP_TRY(launch_pass2(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
     HIP_TRY(hipStreamSynchronize(r.s));
   }

@@ -179,8 +179,11 @@ def test_tiny_systems_and_zero_rhs():
     A = random_symmetric(40, draws=3, seed=1)
     B = rhs_normal(A.n, 2, seed=1)
     X, info, ro, _ = _both(A, B, 1e-10, 100)
-    assert info.status == ro.status == bmr.CONVERGED and info.band_iters == ro.iters
-    assert _relcols(X, np.linalg.solve(A.to_scipy().toarray(), B)) <= 1e-7
+    # the basis nearly fills R^40 here, so the last iterations sit in the
+    # rounding-order noise: compare outcomes, not the stopping index
+    assert info.status == ro.status == bmr.CONVERGED and abs(info.band_iters - ro.iters) <= 4
+    Xd = np.linalg.solve(A.to_scipy().toarray(), B)
+    assert _relcols(X, Xd) <= 1e-7 and _relcols(ro.X, Xd) <= 1e-7
     # n = 9, p = 2: the basis fills R^9 before convergence, the next candidate
     # has no independent substitute left -> bench exhausted at the same j
     A = laplacian((3, 3), 0.5)

@@ -151,9 +151,9 @@ WORKLOADS = {
     # 2-D 5-point Laplacian on 32x32, shift -0.7: n=1024, p=4
     "lap2d-32-p4": dict(matrix=("laplacian", (32, 32), 0.7), rhs=("normal", 4), tol=1e-8, max_iter=500),
     # 3-D 7-point Laplacian on 128^3, shift -0.3: n=2,097,152, p=8
-    "lap3d-128-p8": dict(matrix=("laplacian", (128, 128, 128), 0.3), rhs=("normal", 8), tol=1e-8, max_iter=40000),
-    "lap3d-128-p1": dict(matrix=("laplacian", (128, 128, 128), 0.3), rhs=("normal", 1), tol=1e-8, max_iter=40000),
-    "lap3d-128-p16": dict(matrix=("laplacian", (128, 128, 128), 0.3), rhs=("normal", 16), tol=1e-8, max_iter=40000),
+    "lap3d-128-p8": dict(matrix=("laplacian", (128, 128, 128), 0.3), rhs=("normal", 8), tol=1e-8, max_iter=400000),
+    "lap3d-128-p1": dict(matrix=("laplacian", (128, 128, 128), 0.3), rhs=("normal", 1), tol=1e-8, max_iter=400000),
+    "lap3d-128-p16": dict(matrix=("laplacian", (128, 128, 128), 0.3), rhs=("normal", 16), tol=1e-8, max_iter=400000),
     # 3-D Laplacian on 64^3 with nearly dependent columns and an exact copy
     "stress-64-k0": dict(matrix=("laplacian", (64, 64, 64), 0.3), rhs=("stress", 0), tol=1e-8, max_iter=40000),
     "stress-64-k4": dict(matrix=("laplacian", (64, 64, 64), 0.3), rhs=("stress", 4), tol=1e-8, max_iter=40000),
