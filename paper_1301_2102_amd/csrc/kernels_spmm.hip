@@ -29,7 +29,7 @@ namespace bmr {
 namespace {
 
 constexpr int WG = 256;
-constexpr int PASS1_MAX_WG = 4096;
+constexpr int PASS1_MAX_WG = 2048;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Row layout for block size p: one lane per row for p <= 2; otherwise a group
@@ -171,27 +171,42 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   const double* __restrict__ Vp = Vbase + (size_t)((k + 2) % 3) * slot;  // V_{k-1}
   double* __restrict__ W = Vbase + (size_t)((k + 1) % 3) * slot;         // becomes V_{k+1}
   const int nb = st->nb, taken = st->taken;
+  const bool live_bench = taken < nb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane / LPR, c = lane % LPR;
   const int c0 = c * CPL;  // first column of this lane
 
-  __shared__ double sBp[P][P + 1];  // B_{k-1}, padded against bank conflicts
-  constexpr int SR = LN::ROW ? 1 : RPW;
-  __shared__ double sv[WG / 64][SR][16], sw[WG / 64][SR][16];  // staged rows of [V_k W]
+  // LDS: B_{k-1} (padded against bank conflicts), then one region that holds
+  // the per-wavefront staging of [V_k W], V_{k-1} and the bench rows during
+  // the row loop and the per-wavefront partial sums afterwards
+  constexpr int SR = LN::ROW ? 1 : RPW;  // staged rows per wavefront
+  constexpr int SC = P <= 8 ? 8 : 16;    // staged columns of V_k and W
+  constexpr int STAGE = SR * (2 * SC + P + MAXB);
+  constexpr int NEP = n_entries(P, MAXB);
+  constexpr int PER_WAVE = STAGE > NEP ? STAGE : NEP;
+  __shared__ double sBp[P][P + 1];
+  __shared__ double smem[WG / 64][PER_WAVE];
+  double* sv = smem[wave];          // [SR][SC]
+  double* sw = sv + SR * SC;        // [SR][SC]
+  double* svp = sw + SR * SC;       // [SR][P]
+  double* sg = svp + SR * P;        // [SR][MAXB]
   for (int e = tid; e < P * P; e += WG) sBp[e / P][e % P] = st->Bprev[(e / P) * MAXP + (e % P)];
   __syncthreads();
 
   constexpr int NGG = (MAXB * MAXB + LPR - 1) / LPR;
-  double aA[CPL], aWg[CPL][MAXB], aVg[CPL][MAXB], aGg[NGG];
-  double lG[CPL][CPL], lQ[CPL][CPL], lP[CPL][CPL];  // one-lane-per-row Grams (p <= 2)
-  dbl4 m0 = {0, 0, 0, 0}, m1 = {0, 0, 0, 0}, m2 = {0, 0, 0, 0};  // matrix-core Grams
+  double aA[CPL], aGg[NGG];
+  // one-lane-per-row (p <= 2) accumulators
+  double lG[CPL][CPL], lQ[CPL][CPL], lP[CPL][CPL], lWg[CPL][MAXB], lVg[CPL][MAXB];
+  // matrix-core accumulators: p <= 8: m0 = X^T X, m1 = X^T g with X = [V_k W];
+  // p > 8: V^T V, V^T W, W^T W, V^T g, W^T g
+  dbl4 m0 = {0, 0, 0, 0}, m1 = {0, 0, 0, 0}, m2 = {0, 0, 0, 0}, m3 = {0, 0, 0, 0}, m4 = {0, 0, 0, 0};
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
     aA[cc] = 0.0;
 #pragma unroll
-    for (int b = 0; b < MAXB; ++b) aWg[cc][b] = aVg[cc][b] = 0.0;
-#pragma unroll
     for (int r = 0; r < CPL; ++r) lG[cc][r] = lQ[cc][r] = lP[cc][r] = 0.0;
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) lWg[cc][b] = lVg[cc][b] = 0.0;
   }
 #pragma unroll
   for (int q = 0; q < NGG; ++q) aGg[q] = 0.0;
@@ -205,69 +220,26 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
     const bool valid = row < r1;
     double a[CPL];
     gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
-    // this lane's values of V_k, and the whole row of V_{k-1}
-    double v[CPL], w[CPL], vp[P];
-    if (valid && c0 < P) {
-      vload<CPL>(V + row * P + c0, v);
-    } else {
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) v[cc] = 0.0;
-    }
-    if (valid) {
-      if constexpr (P % 2 == 0) {
-#pragma unroll
-        for (int r = 0; r < P; r += 2) {
-          const double2 t = *reinterpret_cast<const double2*>(Vp + row * P + r);
-          vp[r] = t.x;
-          vp[r + 1] = t.y;
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < P; ++r) vp[r] = Vp[row * P + r];
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < P; ++r) vp[r] = 0.0;
-    }
-    // known coefficients by symmetry: column l loses sum_{r >= l} B_{k-1}(l, r) V_{k-1}(:, r)
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) {
-      const int col = c0 + cc;
-      double t = a[cc];
-#pragma unroll
-      for (int r = 0; r < P; ++r)
-        if (r >= col && col < P) t = fma(-sBp[col][r], vp[r], t);
-      w[cc] = t;
-      aA[cc] = fma(a[cc], a[cc], aA[cc]);
-    }
-    if (valid && c0 < P) {
-      if constexpr (CPL == 2) {
-        *reinterpret_cast<double2*>(W + row * P + c0) = make_double2(w[0], w[1]);
-      } else {
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) W[row * P + c0 + cc] = w[cc];
-      }
-    }
-    // substitute bench: W^T g, V_k^T g, g^T g
-    if (taken < nb) {
-      double g[MAXB];
-#pragma unroll
-      for (int b = 0; b < MAXB; ++b) g[b] = (b >= taken && b < nb && valid) ? bench[row * nb + b] : 0.0;
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc)
-#pragma unroll
-        for (int b = 0; b < MAXB; ++b) {
-          aWg[cc][b] = fma(w[cc], g[b], aWg[cc][b]);
-          aVg[cc][b] = fma(v[cc], g[b], aVg[cc][b]);
-        }
-#pragma unroll
-      for (int q = 0; q < NGG; ++q) {
-        const int e = c + q * LPR;  // entry (e / MAXB, e % MAXB) of g^T g
-        if (e < MAXB * MAXB) aGg[q] = fma(g[e / MAXB], g[e % MAXB], aGg[q]);
-      }
-    }
-    // Gram products of the block
+    double v[CPL], w[CPL];
     if constexpr (LN::ROW) {
+      // the lane owns the whole row: everything stays in registers
+      double vp[P], g[MAXB];
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        v[r] = valid ? V[row * P + r] : 0.0;
+        vp[r] = valid ? Vp[row * P + r] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) g[b] = (live_bench && b >= taken && b < nb && valid) ? bench[row * nb + b] : 0.0;
+#pragma unroll
+      for (int col = 0; col < P; ++col) {
+        double t = a[col];
+#pragma unroll
+        for (int r = col; r < P; ++r) t = fma(-sBp[col][r], vp[r], t);
+        w[col] = t;
+        if (valid) W[row * P + col] = t;
+        aA[col] = fma(a[col], a[col], aA[col]);
+      }
 #pragma unroll
       for (int r = 0; r < CPL; ++r)
 #pragma unroll
@@ -276,28 +248,87 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
           lQ[r][cc] = fma(w[r], w[cc], lQ[r][cc]);
           lP[r][cc] = fma(v[r], v[cc], lP[r][cc]);
         }
+      if (live_bench) {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc)
+#pragma unroll
+          for (int b = 0; b < MAXB; ++b) {
+            lWg[cc][b] = fma(w[cc], g[b], lWg[cc][b]);
+            lVg[cc][b] = fma(v[cc], g[b], lVg[cc][b]);
+          }
+#pragma unroll
+        for (int q = 0; q < NGG; ++q) {
+          const int e = q;  // LPR = 1: entry (e / MAXB, e % MAXB)
+          aGg[q] = fma(g[e / MAXB], g[e % MAXB], aGg[q]);
+        }
+      }
     } else {
+      // this lane's columns of V_k and V_{k-1}; its bench entry
+      double vpo[CPL];
+      if (valid && c0 < P) {
+        vload<CPL>(V + row * P + c0, v);
+        vload<CPL>(Vp + row * P + c0, vpo);
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) v[cc] = vpo[cc] = 0.0;
+      }
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc)
+        if (c0 + cc < P) {
+          sv[grp * SC + c0 + cc] = v[cc];
+          svp[grp * P + c0 + cc] = vpo[cc];
+        }
+      if (c < MAXB) sg[grp * MAXB + c] = (live_bench && c >= taken && c < nb && valid) ? bench[row * nb + c] : 0.0;
+      __builtin_amdgcn_wave_barrier();
+      // known coefficients by symmetry: column l loses sum_{r >= l} B_{k-1}(l, r) V_{k-1}(:, r)
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
-        if (c0 + cc < 16) {
-          sv[wave][grp][c0 + cc] = v[cc];
-          sw[wave][grp][c0 + cc] = w[cc];
+        const int col = c0 + cc;
+        double t = a[cc];
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+          if (r >= col && col < P) t = fma(-sBp[col][r], svp[grp * P + r], t);
+        w[cc] = t;
+        if (col < P) sw[grp * SC + col] = t;
+        aA[cc] = fma(a[cc], a[cc], aA[cc]);
+      }
+      if (valid && c0 < P) {
+        if constexpr (CPL == 2) {
+          *reinterpret_cast<double2*>(W + row * P + c0) = make_double2(w[0], w[1]);
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) W[row * P + c0 + cc] = w[cc];
+        }
+      }
+      // g^T g, spread over the lanes of the group
+      if (live_bench) {
+#pragma unroll
+        for (int q = 0; q < NGG; ++q) {
+          const int e = c + q * LPR;
+          if (e < MAXB * MAXB) aGg[q] = fma(sg[grp * MAXB + e / MAXB], sg[grp * MAXB + e % MAXB], aGg[q]);
         }
       }
       __builtin_amdgcn_wave_barrier();
+      // Gram products on the matrix cores, four staged rows per product
       const int m = lane % 16, rq = lane / 16;
 #pragma unroll
       for (int h = 0; h < RPW / 4; ++h) {
         const int rl = 4 * h + rq;
+        const double y = (m < MAXB) ? sg[rl * MAXB + m] : 0.0;  // bench columns (zero when used up)
         if constexpr (P <= 8) {
-          // X = [V_k | W] as 16 columns (zero padded), four rows per product
-          const double x = (m < 8) ? ((m < P) ? sv[wave][rl][m] : 0.0) : ((m - 8 < P) ? sw[wave][rl][m - 8] : 0.0);
+          // X = [V_k | W] as 16 columns (zero padded)
+          const double x = (m < 8) ? ((m < P) ? sv[rl * SC + m] : 0.0) : ((m - 8 < P) ? sw[rl * SC + m - 8] : 0.0);
           m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, m0, 0, 0, 0);
+          if (live_bench) m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, m1, 0, 0, 0);
         } else {
-          const double xv = sv[wave][rl][m], xw = sw[wave][rl][m];
+          const double xv = (m < P) ? sv[rl * SC + m] : 0.0, xw = (m < P) ? sw[rl * SC + m] : 0.0;
           m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xv, m0, 0, 0, 0);  // V^T V
           m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xw, m1, 0, 0, 0);  // V^T W
           m2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xw, xw, m2, 0, 0, 0);  // W^T W
+          if (live_bench) {
+            m3 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, y, m3, 0, 0, 0);  // V^T g
+            m4 = __builtin_amdgcn_mfma_f64_16x16x4f64(xw, y, m4, 0, 0, 0);  // W^T g
+          }
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -305,21 +336,13 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   }
 
   // ---- workgroup reduction: deterministic order --------------------------
-  constexpr int NEP = n_entries(P, MAXB);
-  __shared__ double sred[WG / 64][NEP];
+  __syncthreads();  // the partial sums reuse the staging region
   const int ne = n_entries(P, nb);
-  double* s = sred[wave];
+  double* s = smem[wave];
   for (int e = lane; e < ne; e += 64) s[e] = 0.0;
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
-  for (int cc = 0; cc < CPL; ++cc) {
-    aA[cc] = group_sum<LPR>(aA[cc]);
-#pragma unroll
-    for (int b = 0; b < MAXB; ++b) {
-      aWg[cc][b] = group_sum<LPR>(aWg[cc][b]);
-      aVg[cc][b] = group_sum<LPR>(aVg[cc][b]);
-    }
-  }
+  for (int cc = 0; cc < CPL; ++cc) aA[cc] = group_sum<LPR>(aA[cc]);
 #pragma unroll
   for (int q = 0; q < NGG; ++q) aGg[q] = group_sum<LPR>(aGg[q]);
   if constexpr (LN::ROW) {
@@ -331,6 +354,13 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         lQ[r][cc] = group_sum<1>(lQ[r][cc]);
         lP[r][cc] = group_sum<1>(lP[r][cc]);
       }
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc)
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b) {
+        lWg[cc][b] = group_sum<1>(lWg[cc][b]);
+        lVg[cc][b] = group_sum<1>(lVg[cc][b]);
+      }
     if (lane == 0) {
 #pragma unroll
       for (int r = 0; r < CPL; ++r)
@@ -339,6 +369,11 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
           s[off_G(P) + r * P + cc] = lG[r][cc];
           s[off_Q(P) + r * P + cc] = lQ[r][cc];
           s[off_P(P) + r * P + cc] = lP[r][cc];
+        }
+      for (int cc = 0; cc < CPL; ++cc)
+        for (int b = 0; b < nb; ++b) {
+          s[off_Wg(P) + cc * nb + b] = lWg[cc][b];
+          s[off_Vg(P, nb) + cc * nb + b] = lVg[cc][b];
         }
     }
   } else {
@@ -353,11 +388,19 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         if (rowD < P && colD < P) s[off_P(P) + rowD * P + colD] = d;
         if (rowD < P && colD >= 8 && colD - 8 < P) s[off_G(P) + rowD * P + colD - 8] = d;
         if (rowD >= 8 && rowD - 8 < P && colD >= 8 && colD - 8 < P) s[off_Q(P) + (rowD - 8) * P + colD - 8] = d;
+        if (colD < nb) {
+          if (rowD < P) s[off_Vg(P, nb) + rowD * nb + colD] = m1[i];
+          if (rowD >= 8 && rowD - 8 < P) s[off_Wg(P) + (rowD - 8) * nb + colD] = m1[i];
+        }
       } else {
         if (rowD < P && colD < P) {
           s[off_P(P) + rowD * P + colD] = m0[i];
           s[off_G(P) + rowD * P + colD] = m1[i];
           s[off_Q(P) + rowD * P + colD] = m2[i];
+        }
+        if (rowD < P && colD < nb) {
+          s[off_Vg(P, nb) + rowD * nb + colD] = m3[i];
+          s[off_Wg(P) + rowD * nb + colD] = m4[i];
         }
       }
     }
@@ -366,13 +409,7 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) {
       const int col = c0 + cc;
-      if (col < P) {
-        s[off_a(P) + col] = aA[cc];
-        for (int b = 0; b < nb; ++b) {
-          s[off_Wg(P) + col * nb + b] = aWg[cc][b];
-          s[off_Vg(P, nb) + col * nb + b] = aVg[cc][b];
-        }
-      }
+      if (col < P) s[off_a(P) + col] = aA[cc];
     }
 #pragma unroll
     for (int q = 0; q < NGG; ++q) {
@@ -384,7 +421,7 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   for (int e = tid; e < ne; e += WG) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < WG / 64; ++q) t += sred[q][e];
+    for (int q = 0; q < WG / 64; ++q) t += smem[q][e];
     part[(size_t)e * n_wg + blockIdx.x] = t;
   }
 }
