@@ -14,7 +14,9 @@
  * (Sections 3-5 and Algorithm 7.1 of the paper).
  *
  * Conventions shared by every entry point
- *   - Precision: IEEE binary64 throughout.
+ *   - Precision: the interface is IEEE binary64 throughout.  bmr_solve runs
+ *     either in binary64 (BMR_PREC_FP64) or as a binary32 inner solver inside
+ *     binary64 iterative refinement (BMR_PREC_MIXED, see bmr_opts_t).
  *   - Blocks (B, X, V, W, R) are n x p, row-interleaved: element (i, c) is at
  *     offset i*p + c.  This is a C-contiguous (n, p) array.
  *   - A is CSR with int32 row pointers and column indices, column indices
@@ -42,7 +44,7 @@
 extern "C" {
 #endif
 
-#define BMR_VERSION 10000 /* 1.0.0 */
+#define BMR_VERSION 10100 /* 1.1.0 */
 #define BMR_MAX_P 16      /* largest block size p */
 #define BMR_MAX_BENCH 4   /* largest substitutes bench */
 
@@ -50,6 +52,8 @@ enum bmr_status {
   BMR_CONVERGED = 0,          /* max_i ||b_i - A x_i|| / ||b_i|| < tol (recurrence residual) */
   BMR_MAX_ITER = 1,           /* max_iter band iterations done; X is the last iterate */
   BMR_BENCH_EXHAUSTED = 2,    /* a dependent vector found no substitute; X is the last iterate */
+  BMR_STAGNATED = 3,          /* BMR_PREC_MIXED: a refinement cycle reduced the largest explicit
+                                 relative residual by less than half; X is the last iterate */
   BMR_INVALID_ARG = -1,       /* p outside [1, BMR_MAX_P], n < 1, NULL pointer, tol <= 0, ... */
   BMR_WORKSPACE_TOO_SMALL = -2,
   BMR_HIP_ERROR = -3,         /* a HIP runtime call failed */
@@ -83,8 +87,32 @@ typedef struct bmr_opts {
   int64_t hist_cap;    /* rows of the residual history kept on the device (>= 0).
                           Default 0. */
   uint32_t flags;      /* BMR_FLAG_* bits.  Default 0. */
-  uint32_t _reserved;
+  int32_t precision;   /* BMR_PREC_FP64 (default) or BMR_PREC_MIXED. */
+  double inner_tol;    /* BMR_PREC_MIXED: each refinement cycle runs the FP32 inner solve
+                          until its recurrence residual has dropped by this factor
+                          (or below what the outer tolerance still needs).
+                          0 < inner_tol < 1.  Default 1e-6. */
+  int32_t max_refine;  /* BMR_PREC_MIXED: refinement cycles at most (>= 1).  Default 30. */
+  int32_t _reserved;
 } bmr_opts_t;
+
+/* bmr_opts_t.precision.
+ *
+ * BMR_PREC_FP64: the solver of Algorithm 7.1 in binary64.
+ *
+ * BMR_PREC_MIXED: iterative refinement in binary64 around the same solver
+ * run with binary32 data (not part of the paper).  Each cycle computes the
+ * explicit residual R = B - A X in binary64, stops when every column has
+ * ||r_i|| / ||b_i|| < tol, and otherwise solves A D = R with the block
+ * operator, the Gram products, the update pass and all n-length vectors in
+ * binary32 (binary32 accumulation), while the band kernel (Givens QR,
+ * Cholesky of the new block, dependence test, residual recurrence) stays in
+ * binary64; then X += D in binary64.  The inner dependence tolerance is
+ * max(gamma, 1e-5), the level at which binary32 data cannot tell a dependent
+ * candidate from rounding noise.  The stopping test is on the explicit
+ * binary64 residual, not on the recurrence. */
+#define BMR_PREC_FP64 0
+#define BMR_PREC_MIXED 1
 
 /* bmr_opts_t.flags: time every kernel of every block iteration with HIP
  * events on the solve stream (one block iteration in flight at a time; the
@@ -106,6 +134,10 @@ typedef struct bmr_stats {
    * pass) and the number of block iterations timed */
   double t_kernel_ms[4];
   int64_t n_profiled;
+  int32_t precision;       /* the bmr_opts_t.precision the solve ran with */
+  int32_t n_refine;        /* BMR_PREC_MIXED: refinement cycles run (inner solves) */
+  double res_true[BMR_MAX_P]; /* BMR_PREC_MIXED: final explicit ||b_i - A x_i|| / ||b_i||
+                                 in binary64 (also copied to res_rec); 0 for BMR_PREC_FP64 */
 } bmr_stats_t;
 
 /* Library version, BMR_VERSION of the build. */
@@ -118,10 +150,12 @@ const char* bmr_status_string(int status);
 void bmr_default_opts(bmr_opts_t* opts);
 
 /* Bytes of device workspace bmr_solve and bmr_residual need for a system of
- * n rows, block size p and the given options (opts may be NULL for defaults).
- * bytes: host output.  Returns BMR_INVALID_ARG for p outside [1, BMR_MAX_P],
- * n < 1 or n_bench outside [0, BMR_MAX_BENCH]. */
-int bmr_workspace_bytes(int64_t n, int p, const bmr_opts_t* opts, size_t* bytes);
+ * n rows, nnz stored matrix entries, block size p and the given options (opts
+ * may be NULL for defaults; nnz only matters for BMR_PREC_MIXED, which keeps a
+ * binary32 copy of the matrix values).  bytes: host output.  Returns
+ * BMR_INVALID_ARG for p outside [1, BMR_MAX_P], n < 1, nnz < 0 or invalid
+ * options. */
+int bmr_workspace_bytes(int64_t n, int64_t nnz, int p, const bmr_opts_t* opts, size_t* bytes);
 
 /* Solve A X = B with X_0 = 0 (eq. (1.1); Algorithm 7.1 inputs and outputs).
  *
@@ -131,16 +165,21 @@ int bmr_workspace_bytes(int64_t n, int p, const bmr_opts_t* opts, size_t* bytes)
  *              alias B or the workspace.
  *   p          block size, 1 <= p <= BMR_MAX_P.
  *   opts       host, may be NULL (defaults).
- *   workspace  device, at least bmr_workspace_bytes(n, p, opts) bytes,
+ *   workspace  device, at least bmr_workspace_bytes(n, A->nnz, p, opts) bytes,
  *              256-byte aligned; contents on entry are ignored.
  *   stream     HIP stream all work is enqueued on.
  *   stats      host, may be NULL.
  *   res_hist   host, may be NULL; else at least opts->hist_cap * p doubles.
- *              Row j-1 receives rho_j^{(i)} / ||b_i|| (eq. (3.5)) for band
- *              iterations j = 1 .. min(band_iters, hist_cap); 0 where b_i = 0.
+ *              BMR_PREC_FP64: row j-1 receives rho_j^{(i)} / ||b_i|| (eq. (3.5))
+ *              for band iterations j = 1 .. min(band_iters, hist_cap).
+ *              BMR_PREC_MIXED: row c-1 receives the explicit relative residual
+ *              ||b_i - A x_i|| / ||b_i|| after refinement cycle c.
+ *              0 where b_i = 0.
  *
- * The stream is synchronised before return.  Status: BMR_CONVERGED,
- * BMR_MAX_ITER, BMR_BENCH_EXHAUSTED or an error code. */
+ * B and X must be 16-byte aligned.  The stream is synchronised before return.
+ * Status: BMR_CONVERGED, BMR_MAX_ITER, BMR_BENCH_EXHAUSTED, BMR_STAGNATED or
+ * an error code.  With BMR_PREC_MIXED, band_iters and block_iters count all
+ * inner solves, and max_iter bounds their sum. */
 int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_opts_t* opts,
               void* workspace, size_t workspace_bytes, hipStream_t stream, bmr_stats_t* stats,
               double* res_hist);
@@ -151,12 +190,18 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
  * after enqueueing on stream. */
 int bmr_spmm(const bmr_csr_t* A, const double* V, double* W, int p, hipStream_t stream);
 
+/* W = A V in binary32 (the block operator of the mixed-precision inner
+ * solve): the structure of A with the binary32 values val32 (device, nnz
+ * entries), V and W device n x p binary32 row-interleaved, not aliasing.
+ * Products and sums in binary32.  Asynchronous. */
+int bmr_spmm_f32(const bmr_csr_t* A, const float* val32, const float* V, float* W, int p, hipStream_t stream);
+
 /* Explicit residual R = B - A X and its column norms (the quantity the
  * stopping test of Algorithm 7.1 bounds).
  *   B, X       device, n x p row-interleaved.
  *   R          device n x p output, or NULL to compute the norms only.
  *   norms      host, p doubles: ||b_i - A x_i||.
- *   workspace  device, >= bmr_workspace_bytes(n, p, NULL) bytes.
+ *   workspace  device, >= bmr_workspace_bytes(n, 0, p, NULL) bytes.
  * Synchronises the stream. */
 int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, double* R,
                  double* norms, void* workspace, size_t workspace_bytes, hipStream_t stream);

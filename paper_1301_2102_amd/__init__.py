@@ -23,6 +23,7 @@ MAX_BENCH = 4
 CONVERGED = 0
 MAX_ITER = 1
 BENCH_EXHAUSTED = 2
+STAGNATED = 3
 INVALID_ARG = -1
 WORKSPACE_TOO_SMALL = -2
 HIP_ERROR = -3
@@ -38,21 +39,26 @@ class _Csr(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("gamma", ctypes.c_double),
                 ("n_bench", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("hist_cap", ctypes.c_int64), ("flags", ctypes.c_uint32), ("_reserved", ctypes.c_uint32)]
+                ("hist_cap", ctypes.c_int64), ("flags", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("_reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_replaced", ctypes.c_int32), ("band_iters", ctypes.c_int64),
                 ("block_iters", ctypes.c_int64), ("n_explicit_qr", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("res_rec", ctypes.c_double * MAX_P), ("time_ms", ctypes.c_double),
-                ("t_kernel_ms", ctypes.c_double * 4), ("n_profiled", ctypes.c_int64)]
+                ("t_kernel_ms", ctypes.c_double * 4), ("n_profiled", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32), ("res_true", ctypes.c_double * MAX_P)]
 
 FLAG_PROFILE = 1
+PREC_FP64 = 0
+PREC_MIXED = 1
+_PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 KERNEL_NAMES = ("pass1_spmm_gram", "reduce", "band", "pass2_update")
 
 
 EXPORTS = ("bmr_version", "bmr_status_string", "bmr_default_opts", "bmr_workspace_bytes", "bmr_solve",
-           "bmr_spmm", "bmr_residual")
+           "bmr_spmm", "bmr_spmm_f32", "bmr_residual")
 
 _lib = None
 
@@ -73,12 +79,14 @@ def load(path: str = LIB_PATH):
     lib.bmr_default_opts.restype = None
     lib.bmr_default_opts.argtypes = [ctypes.POINTER(_Opts)]
     lib.bmr_workspace_bytes.restype = i32
-    lib.bmr_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(_Opts), ctypes.POINTER(sz)]
+    lib.bmr_workspace_bytes.argtypes = [i64, i64, i32, ctypes.POINTER(_Opts), ctypes.POINTER(sz)]
     lib.bmr_solve.restype = i32
     lib.bmr_solve.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, ctypes.POINTER(_Opts), vp, sz, vp,
                               ctypes.POINTER(_Stats), vp]
     lib.bmr_spmm.restype = i32
     lib.bmr_spmm.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp]
+    lib.bmr_spmm_f32.restype = i32
+    lib.bmr_spmm_f32.argtypes = [ctypes.POINTER(_Csr), vp, vp, vp, i32, vp]
     lib.bmr_residual.restype = i32
     lib.bmr_residual.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     _lib = lib
@@ -128,26 +136,37 @@ def _stream_handle(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def _check_block(t, n, name):
+def _check_block(t, n, name, dtype=None):
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.dim() == 2
+    dtype = torch.float64 if dtype is None else dtype
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.dim() == 2
             and t.shape[0] == n and t.is_contiguous()):
-        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape (n, p)")
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape (n, p)")
 
 
-def _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, flags=0) -> _Opts:
+def _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, flags=0, precision="fp64", inner_tol=None,
+          max_refine=None) -> _Opts:
     o = _Opts()
     load().bmr_default_opts(ctypes.byref(o))
     o.tol, o.max_iter, o.gamma, o.n_bench = float(tol), int(max_iter), float(gamma), int(n_bench)
     o.seed, o.hist_cap, o.poll_every = int(seed) & 0xFFFFFFFFFFFFFFFF, int(hist_cap), int(poll_every)
     o.flags = int(flags)
+    if precision not in _PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
+    o.precision = _PRECISIONS[precision]
+    if inner_tol is not None:
+        o.inner_tol = float(inner_tol)
+    if max_refine is not None:
+        o.max_refine = int(max_refine)
     return o
 
 
-def workspace_bytes(n: int, p: int, n_bench: int = 2, hist_cap: int = 0) -> int:
-    o = _opts(1e-8, 1, 1e-10, n_bench, 0, hist_cap, 0)
+def workspace_bytes(n: int, p: int, n_bench: int = 2, hist_cap: int = 0, nnz: int = 0,
+                    precision: str = "fp64") -> int:
+    """Device workspace bytes of a solve (nnz matters for precision="mixed")."""
+    o = _opts(1e-8, 1, 1e-10, n_bench, 0, hist_cap, 0, precision=precision)
     out = ctypes.c_size_t()
-    st = load().bmr_workspace_bytes(int(n), int(p), ctypes.byref(o), ctypes.byref(out))
+    st = load().bmr_workspace_bytes(int(n), int(nnz), int(p), ctypes.byref(o), ctypes.byref(out))
     if st != 0:
         raise BmrError(st, "bmr_workspace_bytes")
     return int(out.value)
@@ -164,6 +183,9 @@ class SolveInfo:
     time_ms: float
     hist: Optional[np.ndarray] = None
     kernel_ms: Optional[dict] = None   # mean ms per block iteration (profile=True)
+    precision: str = "fp64"
+    n_refine: int = 0                  # refinement cycles (precision="mixed")
+    res_true: Optional[np.ndarray] = None  # final explicit relative residual (precision="mixed")
 
     @property
     def status_name(self) -> str:
@@ -172,10 +194,14 @@ class SolveInfo:
 
 def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: float = 1e-10, n_bench: int = 2,
           seed: int = 0, hist_cap: int = 0, poll_every: int = 0, X=None, workspace=None, check: bool = True,
-          profile: bool = False):
+          profile: bool = False, precision: str = "fp64", inner_tol: Optional[float] = None,
+          max_refine: Optional[int] = None):
     """Solve A X = B (A symmetric) by band-Lanczos block MINRES on the GPU.
 
     B: contiguous float64 (n, p) CUDA tensor.  Returns (X, SolveInfo).
+    precision="mixed" runs the FP32 inner solver inside FP64 iterative
+    refinement (inner_tol, max_refine: see bmr_opts_t); its hist rows are the
+    explicit relative residuals after each refinement cycle.
     Errors (negative status) raise BmrError when ``check`` is true.
     """
     import torch
@@ -186,9 +212,10 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
     if X is None:
         X = torch.empty_like(B)
     _check_block(X, n, "X")
-    o = _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, FLAG_PROFILE if profile else 0)
+    o = _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, FLAG_PROFILE if profile else 0,
+              precision, inner_tol, max_refine)
     need = ctypes.c_size_t()
-    st = lib.bmr_workspace_bytes(n, p, ctypes.byref(o), ctypes.byref(need))
+    st = lib.bmr_workspace_bytes(n, A.nnz, p, ctypes.byref(o), ctypes.byref(need))
     if st != 0:
         if check:
             raise BmrError(st, "bmr_workspace_bytes")
@@ -205,8 +232,12 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
         raise BmrError(st, "bmr_solve")
     info = SolveInfo(int(stats.status), int(stats.band_iters), int(stats.block_iters), int(stats.n_replaced),
                      int(stats.n_explicit_qr), np.array(stats.res_rec[:p]), float(stats.time_ms))
+    info.precision = precision
+    if precision == "mixed":
+        info.n_refine = int(stats.n_refine)
+        info.res_true = np.array(stats.res_true[:p])
     if hist is not None:
-        info.hist = hist[:min(info.band_iters, hist_cap)]
+        info.hist = hist[:min(info.n_refine if precision == "mixed" else info.band_iters, hist_cap)]
     if profile:
         info.kernel_ms = dict(zip(KERNEL_NAMES, list(stats.t_kernel_ms)))
         info.kernel_ms["n_block_iters"] = int(stats.n_profiled)
@@ -223,6 +254,25 @@ def spmm(A: DeviceCsr, V, W=None):
     st = load().bmr_spmm(ctypes.byref(Ac), V.data_ptr(), W.data_ptr(), int(V.shape[1]), _stream_handle(V.device))
     if st != 0:
         raise BmrError(st, "bmr_spmm")
+    return W
+
+
+def spmm_f32(A: DeviceCsr, val32, V, W=None):
+    """W = A V in FP32: A's structure with the float32 values val32 (CUDA
+    tensor, nnz entries), V a contiguous float32 (n, p) CUDA tensor."""
+    import torch
+    _check_block(V, A.n, "V", torch.float32)
+    if not (isinstance(val32, torch.Tensor) and val32.is_cuda and val32.dtype == torch.float32
+            and val32.numel() == A.nnz and val32.is_contiguous()):
+        raise ValueError("val32 must be a contiguous float32 CUDA tensor with nnz entries")
+    if W is None:
+        W = torch.empty_like(V)
+    _check_block(W, A.n, "W", torch.float32)
+    Ac = A._c()
+    st = load().bmr_spmm_f32(ctypes.byref(Ac), val32.data_ptr(), V.data_ptr(), W.data_ptr(), int(V.shape[1]),
+                             _stream_handle(V.device))
+    if st != 0:
+        raise BmrError(st, "bmr_spmm_f32")
     return W
 
 

@@ -79,36 +79,54 @@ struct DevState {
   double rho[MAXP];           // last rho_j / beta
 };
 
-// Workspace carve-up (device pointers into the caller's workspace).
+// Workspace carve-up (offsets into the caller's workspace).  The blocks V, M
+// and the bench hold the storage type of the solve (8 bytes for FP64, 4 for
+// the FP32 inner solve of BMR_PREC_MIXED); the mixed-precision solver also
+// keeps the FP32 matrix values, the FP32 correction D and the FP64 residual R.
 struct Layout {
-  size_t off_state, off_red, off_part, off_hist, off_V, off_M, off_bench, total;
+  size_t off_state, off_red, off_part, off_hist, off_V, off_M, off_bench;
+  size_t off_val32, off_D, off_R;  // BMR_PREC_MIXED only
+  size_t total;
   int n_wg;  // workgroups of pass 1 (partials)
 };
 
-Layout layout_for(int64_t n, int p, int nb, int64_t hist_cap);
+Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision);
 int pass1_grid(int64_t n, int p);
 
 // ---- launch wrappers (kernels_*.hip) ------------------------------------
-hipError_t launch_pass1(int p, const bmr_csr_t& A, double* Vbase, size_t slot_elems, double* bench,
+// T = double (FP64 solve) or float (inner solve of the mixed-precision solver);
+// val holds the matrix values in T (A.val itself for double).
+template <typename T>
+hipError_t launch_pass1(int p, const bmr_csr_t& A, const T* val, T* Vbase, size_t slot_elems, const T* bench,
                         double* part, int n_wg, DevState* st, hipStream_t s);
-hipError_t launch_spmm(int p, const bmr_csr_t& A, const double* V, double* W, hipStream_t s);
+template <typename T>
+hipError_t launch_spmm(int p, const bmr_csr_t& A, const T* val, const T* V, T* W, hipStream_t s);
 hipError_t launch_residual(int p, const bmr_csr_t& A, const double* B, const double* X, double* R,
                            double* part, int n_wg, hipStream_t s);
 hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, DevState* st, int check_halt,
                          hipStream_t s);
 hipError_t launch_band(int p, int mode, const double* red, double* hist, DevState* st, hipStream_t s);
-hipError_t launch_pass2(int p, double* Vbase, double* Mbase, size_t slot_elems, double* X, double* bench,
-                        int64_t n, DevState* st, hipStream_t s);
-hipError_t launch_fill(double* x, size_t count, double v, hipStream_t s);
-hipError_t launch_bench_init(double* bench, int64_t n, int nb, uint64_t seed, hipStream_t s);
-// Column kernels of the column-wise (explicit) QR path.
+template <typename T>
+hipError_t launch_pass2(int p, T* Vbase, T* Mbase, size_t slot_elems, T* X, T* bench, int64_t n, DevState* st,
+                        hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s);
+template <typename T>
+hipError_t launch_bench_init(T* bench, int64_t n, int nb, uint64_t seed, hipStream_t s);
+// Column kernels of the column-wise (explicit) QR path, FP64 arithmetic.
 //   coldots: part[wg * (m+1) + r] = sum_i X[i*ldx + r] * Y[i*ldy + yc] (r < m), last = sum Y^2
-hipError_t launch_coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m, int64_t n,
-                          double* part, int n_wg, hipStream_t s);
+template <typename T>
+hipError_t launch_coldots(const T* Y, int ldy, int yc, const T* X, int ldx, int m, int64_t n, double* part,
+                          int n_wg, hipStream_t s);
 struct ColCoef { double c[MAXP]; };
 //   colop: D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef.c[r] * X[i*ldx + r]) / div
-hipError_t launch_colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx,
-                        int m, ColCoef coef, double div, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m,
+                        ColCoef coef, double div, int64_t n, hipStream_t s);
 int coldots_grid(int64_t n);
+// Conversions of the mixed-precision solver: dst = (float)src; x += (double)d; dst = src.
+hipError_t launch_to_f32(const double* src, float* dst, size_t count, hipStream_t s);
+hipError_t launch_add_f32(double* x, const float* d, size_t count, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s);
 
 }  // namespace bmr

@@ -21,6 +21,12 @@
 // 16 x 16 accumulator collects X^T X for X = [V_k W] (p <= 8) or one product
 // per accumulator (p > 8).  The accumulators stay in registers for the whole
 // row range of the workgroup.
+//
+// Every kernel is a template over the storage type T of the blocks and of the
+// matrix values: double for the FP64 solver, float for the inner solve of the
+// mixed-precision solver, where the block operator and the Gram products run
+// in FP32 with FP32 accumulation (V_MFMA_F32_16X16X4F32); the per-workgroup
+// partial sums are handed on in FP64 in both cases.
 #include <algorithm>
 
 #include "bmr_internal.hpp"
@@ -31,6 +37,28 @@ namespace {
 constexpr int WG = 256;
 constexpr int PASS1_MAX_WG = 2048;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Per-type vector and matrix-core helpers.
+template <typename T>
+struct TypeOps;
+template <>
+struct TypeOps<double> {
+  using v2 = double2;
+  using acc4 = dbl4;
+  __device__ static acc4 mfma(double a, double b, acc4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // accumulator layout (measured on gfx950): element i of lane l holds row
+  // 4*i + l/16, column l%16 of the 16 x 16 product
+  __device__ static int acc_row(int lane, int i) { return 4 * i + lane / 16; }
+};
+template <>
+struct TypeOps<float> {
+  using v2 = float2;
+  using acc4 = flt4;
+  __device__ static acc4 mfma(float a, float b, acc4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // measured on gfx950: element i of lane l holds row 4*(l/16) + i, column l%16
+  __device__ static int acc_row(int lane, int i) { return 4 * (lane / 16) + i; }
+};
 
 // Row layout for block size p: one lane per row for p <= 2; otherwise a group
 // of lpr lanes per row with cpl adjacent columns per lane.
@@ -49,13 +77,11 @@ struct Lanes {
   static constexpr int RPG = layout_rpg(P);          // rows per workgroup step
 };
 
-__device__ inline double shfl_d(double x, int src, int width) { return __shfl(x, src, width); }
-
-// x[0..CPL) = V[off .. off + CPL) as one vector load
-template <int CPL>
-__device__ inline void vload(const double* __restrict__ p, double (&x)[CPL]) {
+// x[0..CPL) = p[0 .. CPL) as one vector load (p is 2-element aligned when CPL = 2)
+template <int CPL, typename T>
+__device__ inline void vload(const T* __restrict__ p, T (&x)[CPL]) {
   if constexpr (CPL == 2) {
-    const double2 v = *reinterpret_cast<const double2*>(p);
+    const typename TypeOps<T>::v2 v = *reinterpret_cast<const typename TypeOps<T>::v2*>(p);
     x[0] = v.x;
     x[1] = v.y;
   } else {
@@ -64,15 +90,28 @@ __device__ inline void vload(const double* __restrict__ p, double (&x)[CPL]) {
   }
 }
 
+template <int CPL, typename T>
+__device__ inline void vstore(T* __restrict__ p, const T (&x)[CPL]) {
+  if constexpr (CPL == 2) {
+    typename TypeOps<T>::v2 v;
+    v.x = x[0];
+    v.y = x[1];
+    *reinterpret_cast<typename TypeOps<T>::v2*>(p) = v;
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) p[k] = x[k];
+  }
+}
+
 // acc[k] = sum over the entries of `row` of val * V[col*P + c0 + k], in CSR
 // order (c0 = c * CPL).  In the group layout all lanes of a group call this
 // with the same row; lanes whose columns lie beyond p return zeros.
-template <int P, int LPR, int CPL>
+template <int P, int LPR, int CPL, typename T>
 __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                  const double* __restrict__ va, const double* __restrict__ V, int64_t row,
-                                  bool valid, int c, double (&acc)[CPL]) {
+                                  const T* __restrict__ va, const T* __restrict__ V, int64_t row, bool valid, int c,
+                                  T (&acc)[CPL]) {
 #pragma unroll
-  for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
+  for (int k = 0; k < CPL; ++k) acc[k] = T(0);
   int s = 0, e = 0;
   if (valid) {
     s = rp[row];
@@ -82,12 +121,12 @@ __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t*
     constexpr int U = 8;
     for (int q = s; q < e; q += U) {
       int cq[U];
-      double vq[U], x[U][CPL];
+      T vq[U], x[U][CPL];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool in = q + u < e;
         cq[u] = in ? ci[q + u] : 0;
-        vq[u] = in ? va[q + u] : 0.0;
+        vq[u] = in ? va[q + u] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -95,7 +134,7 @@ __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t*
           vload<CPL>(V + (int64_t)cq[u] * P, x[u]);
         } else {
 #pragma unroll
-          for (int k = 0; k < CPL; ++k) x[u][k] = 0.0;
+          for (int k = 0; k < CPL; ++k) x[u][k] = T(0);
         }
       }
 #pragma unroll
@@ -109,25 +148,25 @@ __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t*
     for (int base = s; base < e; base += LPR) {
       const int idx = base + c;
       int col = 0;
-      double v = 0.0;
+      T v = T(0);
       if (idx < e) {
         col = ci[idx];
         v = va[idx];
       }
       const int cnt = min(LPR, e - base);
       for (int q0 = 0; q0 < cnt; q0 += U) {
-        double co[U], x[U][CPL];
+        T co[U], x[U][CPL];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int cq = __shfl(col, q0 + u, LPR);
-          const double vq = shfl_d(v, q0 + u, LPR);
+          const T vq = __shfl(v, q0 + u, LPR);
           const bool in = q0 + u < cnt;
-          co[u] = in ? vq : 0.0;
+          co[u] = in ? vq : T(0);
           if (in && mine) {
             vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
           } else {
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) x[u][k] = 0.0;
+            for (int k = 0; k < CPL; ++k) x[u][k] = T(0);
           }
         }
 #pragma unroll
@@ -151,25 +190,27 @@ __device__ inline void row_range(int64_t n, int n_wg, int L, int64_t& r0, int64_
 
 // Sum x over the groups of a wavefront (lanes with equal c); the result is
 // valid in every lane.
-template <int LPR>
-__device__ inline double group_sum(double x) {
+template <int LPR, typename T>
+__device__ inline T group_sum(T x) {
 #pragma unroll
   for (int o = LPR; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
 
-template <int P>
+template <int P, typename T>
 __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                              const double* __restrict__ va, int64_t n, double* __restrict__ Vbase,
-                                              size_t slot, const double* __restrict__ bench,
+                                              const T* __restrict__ va, int64_t n, T* __restrict__ Vbase,
+                                              size_t slot, const T* __restrict__ bench,
                                               double* __restrict__ part, int n_wg, DevState* __restrict__ st) {
   if (st->halt) return;
   using LN = Lanes<P>;
+  using Ops = TypeOps<T>;
+  using acc4 = typename Ops::acc4;
   constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int64_t k = st->k;
-  const double* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
-  const double* __restrict__ Vp = Vbase + (size_t)((k + 2) % 3) * slot;  // V_{k-1}
-  double* __restrict__ W = Vbase + (size_t)((k + 1) % 3) * slot;         // becomes V_{k+1}
+  const T* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
+  const T* __restrict__ Vp = Vbase + (size_t)((k + 2) % 3) * slot;  // V_{k-1}
+  T* __restrict__ W = Vbase + (size_t)((k + 1) % 3) * slot;         // becomes V_{k+1}
   const int nb = st->nb, taken = st->taken;
   const bool live_bench = taken < nb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -177,39 +218,39 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   const int c0 = c * CPL;  // first column of this lane
 
   // LDS: B_{k-1} (padded against bank conflicts), then one region that holds
-  // the per-wavefront staging of [V_k W], V_{k-1} and the bench rows during
-  // the row loop and the per-wavefront partial sums afterwards
+  // the per-wavefront staging of [V_k W], V_{k-1} and the bench rows (type T)
+  // during the row loop and the per-wavefront partial sums (double) afterwards
   constexpr int SR = LN::ROW ? 1 : RPW;  // staged rows per wavefront
   constexpr int SC = P <= 8 ? 8 : 16;    // staged columns of V_k and W
-  constexpr int STAGE = SR * (2 * SC + P + MAXB);
+  constexpr int STAGE = (SR * (2 * SC + P + MAXB) * (int)sizeof(T) + 7) / 8;
   constexpr int NEP = n_entries(P, MAXB);
   constexpr int PER_WAVE = STAGE > NEP ? STAGE : NEP;
-  __shared__ double sBp[P][P + 1];
+  __shared__ T sBp[P][P + 1];
   __shared__ double smem[WG / 64][PER_WAVE];
-  double* sv = smem[wave];          // [SR][SC]
-  double* sw = sv + SR * SC;        // [SR][SC]
-  double* svp = sw + SR * SC;       // [SR][P]
-  double* sg = svp + SR * P;        // [SR][MAXB]
-  for (int e = tid; e < P * P; e += WG) sBp[e / P][e % P] = st->Bprev[(e / P) * MAXP + (e % P)];
+  T* sv = reinterpret_cast<T*>(smem[wave]);  // [SR][SC]
+  T* sw = sv + SR * SC;                      // [SR][SC]
+  T* svp = sw + SR * SC;                     // [SR][P]
+  T* sg = svp + SR * P;                      // [SR][MAXB]
+  for (int e = tid; e < P * P; e += WG) sBp[e / P][e % P] = (T)st->Bprev[(e / P) * MAXP + (e % P)];
   __syncthreads();
 
   constexpr int NGG = (MAXB * MAXB + LPR - 1) / LPR;
-  double aA[CPL], aGg[NGG];
+  T aA[CPL], aGg[NGG];
   // one-lane-per-row (p <= 2) accumulators
-  double lG[CPL][CPL], lQ[CPL][CPL], lP[CPL][CPL], lWg[CPL][MAXB], lVg[CPL][MAXB];
+  T lG[CPL][CPL], lQ[CPL][CPL], lP[CPL][CPL], lWg[CPL][MAXB], lVg[CPL][MAXB];
   // matrix-core accumulators: p <= 8: m0 = X^T X, m1 = X^T g with X = [V_k W];
   // p > 8: V^T V, V^T W, W^T W, V^T g, W^T g
-  dbl4 m0 = {0, 0, 0, 0}, m1 = {0, 0, 0, 0}, m2 = {0, 0, 0, 0}, m3 = {0, 0, 0, 0}, m4 = {0, 0, 0, 0};
+  acc4 m0 = {0, 0, 0, 0}, m1 = {0, 0, 0, 0}, m2 = {0, 0, 0, 0}, m3 = {0, 0, 0, 0}, m4 = {0, 0, 0, 0};
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) {
-    aA[cc] = 0.0;
+    aA[cc] = T(0);
 #pragma unroll
-    for (int r = 0; r < CPL; ++r) lG[cc][r] = lQ[cc][r] = lP[cc][r] = 0.0;
+    for (int r = 0; r < CPL; ++r) lG[cc][r] = lQ[cc][r] = lP[cc][r] = T(0);
 #pragma unroll
-    for (int b = 0; b < MAXB; ++b) lWg[cc][b] = lVg[cc][b] = 0.0;
+    for (int b = 0; b < MAXB; ++b) lWg[cc][b] = lVg[cc][b] = T(0);
   }
 #pragma unroll
-  for (int q = 0; q < NGG; ++q) aGg[q] = 0.0;
+  for (int q = 0; q < NGG; ++q) aGg[q] = T(0);
 
   int64_t r0, r1;
   row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
@@ -218,22 +259,22 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
     asm volatile("" ::: "memory");
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
-    double a[CPL];
+    T a[CPL];
     gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
-    double v[CPL], w[CPL];
+    T v[CPL], w[CPL];
     if constexpr (LN::ROW) {
       // the lane owns the whole row: everything stays in registers
-      double vp[P], g[MAXB];
+      T vp[P], g[MAXB];
 #pragma unroll
       for (int r = 0; r < P; ++r) {
-        v[r] = valid ? V[row * P + r] : 0.0;
-        vp[r] = valid ? Vp[row * P + r] : 0.0;
+        v[r] = valid ? V[row * P + r] : T(0);
+        vp[r] = valid ? Vp[row * P + r] : T(0);
       }
 #pragma unroll
-      for (int b = 0; b < MAXB; ++b) g[b] = (live_bench && b >= taken && b < nb && valid) ? bench[row * nb + b] : 0.0;
+      for (int b = 0; b < MAXB; ++b) g[b] = (live_bench && b >= taken && b < nb && valid) ? bench[row * nb + b] : T(0);
 #pragma unroll
       for (int col = 0; col < P; ++col) {
-        double t = a[col];
+        T t = a[col];
 #pragma unroll
         for (int r = col; r < P; ++r) t = fma(-sBp[col][r], vp[r], t);
         w[col] = t;
@@ -264,13 +305,13 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
       }
     } else {
       // this lane's columns of V_k and V_{k-1}; its bench entry
-      double vpo[CPL];
+      T vpo[CPL];
       if (valid && c0 < P) {
         vload<CPL>(V + row * P + c0, v);
         vload<CPL>(Vp + row * P + c0, vpo);
       } else {
 #pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) v[cc] = vpo[cc] = 0.0;
+        for (int cc = 0; cc < CPL; ++cc) v[cc] = vpo[cc] = T(0);
       }
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc)
@@ -278,13 +319,13 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
           sv[grp * SC + c0 + cc] = v[cc];
           svp[grp * P + c0 + cc] = vpo[cc];
         }
-      if (c < MAXB) sg[grp * MAXB + c] = (live_bench && c >= taken && c < nb && valid) ? bench[row * nb + c] : 0.0;
+      if (c < MAXB) sg[grp * MAXB + c] = (live_bench && c >= taken && c < nb && valid) ? bench[row * nb + c] : T(0);
       __builtin_amdgcn_wave_barrier();
       // known coefficients by symmetry: column l loses sum_{r >= l} B_{k-1}(l, r) V_{k-1}(:, r)
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         const int col = c0 + cc;
-        double t = a[cc];
+        T t = a[cc];
 #pragma unroll
         for (int r = 0; r < P; ++r)
           if (r >= col && col < P) t = fma(-sBp[col][r], svp[grp * P + r], t);
@@ -292,14 +333,7 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         if (col < P) sw[grp * SC + col] = t;
         aA[cc] = fma(a[cc], a[cc], aA[cc]);
       }
-      if (valid && c0 < P) {
-        if constexpr (CPL == 2) {
-          *reinterpret_cast<double2*>(W + row * P + c0) = make_double2(w[0], w[1]);
-        } else {
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) W[row * P + c0 + cc] = w[cc];
-        }
-      }
+      if (valid && c0 < P) vstore<CPL>(W + row * P + c0, w);
       // g^T g, spread over the lanes of the group
       if (live_bench) {
 #pragma unroll
@@ -314,20 +348,20 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
 #pragma unroll
       for (int h = 0; h < RPW / 4; ++h) {
         const int rl = 4 * h + rq;
-        const double y = (m < MAXB) ? sg[rl * MAXB + m] : 0.0;  // bench columns (zero when used up)
+        const T y = (m < MAXB) ? sg[rl * MAXB + m] : T(0);  // bench columns (zero when used up)
         if constexpr (P <= 8) {
           // X = [V_k | W] as 16 columns (zero padded)
-          const double x = (m < 8) ? ((m < P) ? sv[rl * SC + m] : 0.0) : ((m - 8 < P) ? sw[rl * SC + m - 8] : 0.0);
-          m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, m0, 0, 0, 0);
-          if (live_bench) m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, m1, 0, 0, 0);
+          const T x = (m < 8) ? ((m < P) ? sv[rl * SC + m] : T(0)) : ((m - 8 < P) ? sw[rl * SC + m - 8] : T(0));
+          m0 = Ops::mfma(x, x, m0);
+          if (live_bench) m1 = Ops::mfma(x, y, m1);
         } else {
-          const double xv = (m < P) ? sv[rl * SC + m] : 0.0, xw = (m < P) ? sw[rl * SC + m] : 0.0;
-          m0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xv, m0, 0, 0, 0);  // V^T V
-          m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, xw, m1, 0, 0, 0);  // V^T W
-          m2 = __builtin_amdgcn_mfma_f64_16x16x4f64(xw, xw, m2, 0, 0, 0);  // W^T W
+          const T xv = (m < P) ? sv[rl * SC + m] : T(0), xw = (m < P) ? sw[rl * SC + m] : T(0);
+          m0 = Ops::mfma(xv, xv, m0);  // V^T V
+          m1 = Ops::mfma(xv, xw, m1);  // V^T W
+          m2 = Ops::mfma(xw, xw, m2);  // W^T W
           if (live_bench) {
-            m3 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, y, m3, 0, 0, 0);  // V^T g
-            m4 = __builtin_amdgcn_mfma_f64_16x16x4f64(xw, y, m4, 0, 0, 0);  // W^T g
+            m3 = Ops::mfma(xv, y, m3);  // V^T g
+            m4 = Ops::mfma(xw, y, m4);  // W^T g
           }
         }
       }
@@ -377,12 +411,10 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         }
     }
   } else {
-    // accumulator layout (measured on gfx950): lane l, element i holds row
-    // 4*i + l/16, column l%16 of the 16 x 16 product
     const int colD = lane % 16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int rowD = 4 * i + lane / 16;
+      const int rowD = Ops::acc_row(lane, i);
       if constexpr (P <= 8) {
         const double d = m0[i];
         if (rowD < P && colD < P) s[off_P(P) + rowD * P + colD] = d;
@@ -426,10 +458,10 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   }
 }
 
-template <int P>
+template <int P, typename T>
 __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                             const double* __restrict__ va, int64_t n, const double* __restrict__ V,
-                                             double* __restrict__ W, int n_wg) {
+                                             const T* __restrict__ va, int64_t n, const T* __restrict__ V,
+                                             T* __restrict__ W, int n_wg) {
   using LN = Lanes<P>;
   constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -439,19 +471,14 @@ __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, con
   for (int64_t base = r0; base < r1; base += RPG) {
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
-    double a[CPL];
+    T a[CPL];
     gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
-    if (valid && c0 < P) {
-      if constexpr (CPL == 2) {
-        *reinterpret_cast<double2*>(W + row * P + c0) = make_double2(a[0], a[1]);
-      } else {
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) W[row * P + c0 + cc] = a[cc];
-      }
-    }
+    if (valid && c0 < P) vstore<CPL>(W + row * P + c0, a);
   }
 }
 
+// R = B - A X and per-workgroup partial sums of the squared column norms, in
+// FP64 (it is also the outer residual of the mixed-precision solver).
 template <int P>
 __global__ __launch_bounds__(WG) void k_residual(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                  const double* __restrict__ va, int64_t n,
@@ -530,23 +557,32 @@ static int spmm_grid(int64_t n, int p) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_pass1(int p, const bmr_csr_t& A, double* Vbase, size_t slot, double* bench, double* part, int n_wg,
-                        DevState* st, hipStream_t s) {
-#define L1(P)                                                                                         \
-  hipLaunchKernelGGL(k_pass1<P>, dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, A.val, A.n, Vbase, \
-                     slot, bench, part, n_wg, st)
+template <typename T>
+hipError_t launch_pass1(int p, const bmr_csr_t& A, const T* val, T* Vbase, size_t slot, const T* bench, double* part,
+                        int n_wg, DevState* st, hipStream_t s) {
+#define L1(P)                                                                                                 \
+  hipLaunchKernelGGL((k_pass1<P, T>), dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, val, A.n, Vbase, slot, \
+                     bench, part, n_wg, st)
   BMR_DISPATCH_P(p, L1)
 #undef L1
   return hipGetLastError();
 }
 
-hipError_t launch_spmm(int p, const bmr_csr_t& A, const double* V, double* W, hipStream_t s) {
+template <typename T>
+hipError_t launch_spmm(int p, const bmr_csr_t& A, const T* val, const T* V, T* W, hipStream_t s) {
   const int n_wg = spmm_grid(A.n, p);
-#define L2(P) hipLaunchKernelGGL(k_spmm<P>, dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, A.val, A.n, V, W, n_wg)
+#define L2(P) hipLaunchKernelGGL((k_spmm<P, T>), dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, val, A.n, V, W, n_wg)
   BMR_DISPATCH_P(p, L2)
 #undef L2
   return hipGetLastError();
 }
+
+template hipError_t launch_pass1<double>(int, const bmr_csr_t&, const double*, double*, size_t, const double*,
+                                         double*, int, DevState*, hipStream_t);
+template hipError_t launch_pass1<float>(int, const bmr_csr_t&, const float*, float*, size_t, const float*, double*,
+                                        int, DevState*, hipStream_t);
+template hipError_t launch_spmm<double>(int, const bmr_csr_t&, const double*, const double*, double*, hipStream_t);
+template hipError_t launch_spmm<float>(int, const bmr_csr_t&, const float*, const float*, float*, hipStream_t);
 
 hipError_t launch_residual(int p, const bmr_csr_t& A, const double* Bm, const double* X, double* R, double* part,
                            int n_wg, hipStream_t s) {

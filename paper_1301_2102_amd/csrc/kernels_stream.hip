@@ -11,7 +11,9 @@
 // Every per-row operation runs in the order of the one-vector-per-iteration
 // algorithm, so that only the inner products differ in rounding.
 // The p x p coefficient blocks come from the band kernel through the device
-// state and are staged in LDS once per workgroup.
+// state and are staged in LDS once per workgroup, rounded to the storage type
+// T (double, or float in the inner solve of the mixed-precision solver, whose
+// row arithmetic then runs in FP32).
 #include "bmr_internal.hpp"
 
 namespace bmr {
@@ -19,37 +21,37 @@ namespace {
 
 constexpr int WG = 256;
 
-template <int P>
-__global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double* __restrict__ Mbase, size_t slot,
-                                              double* __restrict__ X, double* __restrict__ bench, int64_t n,
+template <int P, typename T>
+__global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
+                                              T* __restrict__ X, T* __restrict__ bench, int64_t n,
                                               const DevState* __restrict__ st) {
   const int64_t k = st->k2;
   if (k == 0) return;
-  __shared__ double sA[P * P], sB[P * P], sRa[P * P], sRb[P * P], sRc[P * P], sZ[P * P], sBc[MAXB * P];
+  __shared__ T sA[P * P], sB[P * P], sRa[P * P], sRb[P * P], sRc[P * P], sZ[P * P], sBc[MAXB * P];
   for (int e = threadIdx.x; e < P * P; e += WG) {
     const int r = e / P, c = e % P, o = r * MAXP + c;
-    sA[e] = st->P2A[o];
-    sB[e] = st->P2B[o];
-    sRa[e] = st->Ra[o];
-    sRb[e] = st->Rb[o];
-    sRc[e] = st->Rc[o];
-    sZ[e] = st->Z[o];
+    sA[e] = (T)st->P2A[o];
+    sB[e] = (T)st->P2B[o];
+    sRa[e] = (T)st->Ra[o];
+    sRb[e] = (T)st->Rb[o];
+    sRc[e] = (T)st->Rc[o];
+    sZ[e] = (T)st->Z[o];
   }
-  for (int e = threadIdx.x; e < MAXB * P; e += WG) sBc[e] = st->bcoef[(e / P) * MAXP + (e % P)];
+  for (int e = threadIdx.x; e < MAXB * P; e += WG) sBc[e] = (T)st->bcoef[(e / P) * MAXP + (e % P)];
   __syncthreads();
   const int lstar = st->lstar, nb = st->nb, taken = st->taken;
-  const double* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
-  double* __restrict__ Wn = Vbase + (size_t)((k + 1) % 3) * slot;
-  const double* __restrict__ Mm2 = Mbase + (size_t)((k + 1) % 3) * slot;  // M_{k-2}
-  const double* __restrict__ Mm1 = Mbase + (size_t)((k + 2) % 3) * slot;  // M_{k-1}
-  double* __restrict__ Mk = Mbase + (size_t)(k % 3) * slot;
+  const T* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
+  T* __restrict__ Wn = Vbase + (size_t)((k + 1) % 3) * slot;
+  const T* __restrict__ Mm2 = Mbase + (size_t)((k + 1) % 3) * slot;  // M_{k-2}
+  const T* __restrict__ Mm1 = Mbase + (size_t)((k + 2) % 3) * slot;  // M_{k-1}
+  T* __restrict__ Mk = Mbase + (size_t)(k % 3) * slot;
 
   const int64_t stride = (int64_t)gridDim.x * WG;
   for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
     // re-read the coefficients from LDS in every row rather than holding
     // 6p^2 of them in registers for the whole loop
     asm volatile("" ::: "memory");
-    double v[P], w[P];
+    T v[P], w[P];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       v[c] = V[row * P + c];
@@ -72,26 +74,26 @@ __global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double
     for (int c = 0; c < P; ++c) Wn[row * P + c] = w[c];
     // keep the unused substitutes orthogonal to the new basis vectors
     for (int b = taken; b < nb; ++b) {
-      double g = bench[row * nb + b];
+      T g = bench[row * nb + b];
 #pragma unroll
       for (int l = 0; l < P; ++l) g = fma(-w[l], sBc[b * P + l], g);
       bench[row * nb + b] = g;
     }
     asm volatile("" ::: "memory");
     // search directions of the block
-    double mk[P];
+    T mk[P];
     {
-      double m2[P], m1[P];
+      T m2[P], m1[P];
 #pragma unroll
       for (int c = 0; c < P; ++c) {
         m2[c] = Mm2[row * P + c];
         m1[c] = Mm1[row * P + c];
-        mk[c] = 0.0;
+        mk[c] = T(0);
       }
 #pragma unroll
       for (int l = 0; l < P; ++l) {
         if (l < lstar) {
-          double m = v[l];
+          T m = v[l];
 #pragma unroll
           for (int r = 0; r < P; ++r)
             if (r >= l) m = fma(-sRa[r * P + l], m2[r], m);
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double
     for (int c = 0; c < P; ++c) Mk[row * P + c] = mk[c];
     asm volatile("" ::: "memory");
     // progressive update of the iterate
-    double x[P];
+    T x[P];
 #pragma unroll
     for (int c = 0; c < P; ++c) x[c] = X[row * P + c];
 #pragma unroll
@@ -122,7 +124,8 @@ __global__ __launch_bounds__(WG) void k_pass2(double* __restrict__ Vbase, double
   }
 }
 
-__global__ void k_fill(double* __restrict__ x, size_t count, double v) {
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, size_t count, T v) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) x[i] = v;
 }
@@ -137,18 +140,21 @@ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_bench_init(double* __restrict__ bench, int64_t n, int nb, uint64_t seed) {
+template <typename T>
+__global__ void k_bench_init(T* __restrict__ bench, int64_t n, int nb, uint64_t seed) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     for (int b = 0; b < nb; ++b) {
       const uint64_t bits = splitmix64_at(seed, (uint64_t)b * (uint64_t)n + (uint64_t)i) >> 11;
-      bench[i * nb + b] = 2.0 * ((double)bits * 0x1.0p-53) - 1.0;
+      bench[i * nb + b] = (T)(2.0 * ((double)bits * 0x1.0p-53) - 1.0);
     }
 }
 
 // part[wg*(m+1) + r] = sum_i X[i*ldx + r] * Y[i*ldy + yc] (r < m); part[wg*(m+1) + m] = sum_i Y^2
-__global__ __launch_bounds__(WG) void k_coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m,
-                                                int64_t n, double* __restrict__ part) {
+// (products and sums in FP64 for both storage types)
+template <typename T>
+__global__ __launch_bounds__(WG) void k_coldots(const T* Y, int ldy, int yc, const T* X, int ldx, int m, int64_t n,
+                                                double* __restrict__ part) {
   double acc[MAXP + 1];
 #pragma unroll
   for (int r = 0; r <= MAXP; ++r) acc[r] = 0.0;
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(WG) void k_coldots(const double* Y, int ldy, int yc
     const double y = Y[i * ldy + yc];
 #pragma unroll
     for (int r = 0; r < MAXP; ++r)
-      if (r < m) acc[r] = fma(X[i * ldx + r], y, acc[r]);
+      if (r < m) acc[r] = fma((double)X[i * ldx + r], y, acc[r]);
     acc[MAXP] = fma(y, y, acc[MAXP]);
   }
   __shared__ double sh[WG];
@@ -174,17 +180,37 @@ __global__ __launch_bounds__(WG) void k_coldots(const double* Y, int ldy, int yc
   }
 }
 
-// D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef[r] * X[i*ldx + r]) / div
-// D may be the same column as S (in place) and X may be other columns of the
-// same block, so none of the pointers is restrict-qualified.
-__global__ void k_colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx, int m,
-                        ColCoef coef, double div, int64_t n) {
+// D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef[r] * X[i*ldx + r]) / div,
+// evaluated in FP64 and rounded to T once.  D may be the same column as S (in
+// place) and X may be other columns of the same block, so none of the
+// pointers is restrict-qualified.
+template <typename T>
+__global__ void k_colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m, ColCoef coef,
+                        double div, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double y = S[i * lds + sc];
-    for (int r = 0; r < m; ++r) y = fma(-coef.c[r], X[i * ldx + r], y);
-    D[i * ldd + dc] = y / div;
+    for (int r = 0; r < m; ++r) y = fma(-coef.c[r], (double)X[i * ldx + r], y);
+    D[i * ldd + dc] = (T)(y / div);
   }
+}
+
+// dst[i] = src[i] rounded to float (round to nearest even)
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, size_t count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = (float)src[i];
+}
+
+// x[i] += d[i] in FP64 (the refinement step X += D of the mixed-precision solver)
+__global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ d, size_t count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) x[i] += (double)d[i];
+}
+
+// dst[i] = src[i] (FP64 block copy)
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dst[i] = src[i];
 }
 
 }  // namespace
@@ -224,40 +250,79 @@ static int stream_grid(int64_t n) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_pass2(int p, double* Vbase, double* Mbase, size_t slot, double* X, double* bench, int64_t n,
-                        DevState* st, hipStream_t s) {
+template <typename T>
+hipError_t launch_pass2(int p, T* Vbase, T* Mbase, size_t slot, T* X, T* bench, int64_t n, DevState* st,
+                        hipStream_t s) {
   const int g = stream_grid(n);
-#define L4(P) hipLaunchKernelGGL(k_pass2<P>, dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, bench, n, st)
+#define L4(P) hipLaunchKernelGGL((k_pass2<P, T>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, bench, n, st)
   BMR_DISPATCH_P(p, L4)
 #undef L4
   return hipGetLastError();
 }
 
-hipError_t launch_fill(double* x, size_t count, double v, hipStream_t s) {
-  if (count == 0) return hipSuccess;
+static unsigned flat_grid(size_t count) {
   size_t g = (count + WG - 1) / WG;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)g), dim3(WG), 0, s, x, count, v);
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+template <typename T>
+hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3(flat_grid(count)), dim3(WG), 0, s, x, count, v);
   return hipGetLastError();
 }
 
-hipError_t launch_bench_init(double* bench, int64_t n, int nb, uint64_t seed, hipStream_t s) {
+template <typename T>
+hipError_t launch_bench_init(T* bench, int64_t n, int nb, uint64_t seed, hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bench_init, dim3(stream_grid(n)), dim3(WG), 0, s, bench, n, nb, seed);
+  hipLaunchKernelGGL(k_bench_init<T>, dim3(stream_grid(n)), dim3(WG), 0, s, bench, n, nb, seed);
   return hipGetLastError();
 }
 
-hipError_t launch_coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m, int64_t n, double* part,
-                          int n_wg, hipStream_t s) {
-  hipLaunchKernelGGL(k_coldots, dim3(n_wg), dim3(WG), 0, s, Y, ldy, yc, X, ldx, m, n, part);
+template <typename T>
+hipError_t launch_coldots(const T* Y, int ldy, int yc, const T* X, int ldx, int m, int64_t n, double* part, int n_wg,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_coldots<T>, dim3(n_wg), dim3(WG), 0, s, Y, ldy, yc, X, ldx, m, n, part);
   return hipGetLastError();
 }
 
-hipError_t launch_colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx, int m,
-                        ColCoef coef, double div, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_colop, dim3(stream_grid(n)), dim3(WG), 0, s, D, ldd, dc, S, lds, sc, X, ldx, m, coef, div,
+template <typename T>
+hipError_t launch_colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m, ColCoef coef,
+                        double div, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_colop<T>, dim3(stream_grid(n)), dim3(WG), 0, s, D, ldd, dc, S, lds, sc, X, ldx, m, coef, div,
                      n);
   return hipGetLastError();
 }
+
+hipError_t launch_to_f32(const double* src, float* dst, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3(flat_grid(count)), dim3(WG), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f32(double* x, const float* d, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_f32, dim3(flat_grid(count)), dim3(WG), 0, s, x, d, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(flat_grid(count)), dim3(WG), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+#define BMR_INSTANTIATE(T)                                                                                          \
+  template hipError_t launch_pass2<T>(int, T*, T*, size_t, T*, T*, int64_t, DevState*, hipStream_t);               \
+  template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                                  \
+  template hipError_t launch_bench_init<T>(T*, int64_t, int, uint64_t, hipStream_t);                               \
+  template hipError_t launch_coldots<T>(const T*, int, int, const T*, int, int, int64_t, double*, int, hipStream_t); \
+  template hipError_t launch_colop<T>(T*, int, int, const T*, int, int, const T*, int, int, ColCoef, double, int64_t, \
+                                      hipStream_t);
+BMR_INSTANTIATE(double)
+BMR_INSTANTIATE(float)
+#undef BMR_INSTANTIATE
 
 }  // namespace bmr

@@ -13,6 +13,11 @@
 // kernel rejects the Gram route for a near-dependent block, the device loop
 // halts and the host runs that block's QR column by column (with the
 // dependence test and bench substitution of Section 5.1), then resumes.
+//
+// The block-iteration driver is a template over the storage type of the
+// n-length data: double for BMR_PREC_FP64, float for the inner solves of
+// BMR_PREC_MIXED, whose FP64 iterative-refinement loop (explicit residual,
+// inner solve of A D = R, X += D) sits at the end of this file.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -25,7 +30,15 @@
 namespace bmr {
 namespace {
 
+// The Gram route to the new block's QR is rejected (and the block is
+// orthogonalised column by column instead) when a Cholesky pivot falls below
+// tau_fb * ||A u_j||.  With FP32 Gram products the pivot of a column that
+// lost a fraction t of its norm carries a relative error of about
+// 1e-6 / t^2, hence the larger threshold of the FP32 inner solve.
 constexpr double TAU_FB = 1e-2;
+constexpr double TAU_FB_F32 = 1e-1;
+// Dependence tolerance floor of the FP32 inner solve.
+constexpr double GAMMA_F32 = 1e-5;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t slot_elems(int64_t n, int p) { return ((size_t)n * p + 31) / 32 * 32; }
@@ -42,25 +55,29 @@ static_assert(offsetof(DevState, j) + sizeof(int64_t) == sizeof(Ctl), "Ctl must 
     if (e_ != hipSuccess) return BMR_HIP_ERROR; \
   } while (0)
 
-// Host side of a solve: workspace pointers, stream, scratch for column sums.
+// Host side of a solve in storage type T: workspace pointers, stream,
+// scratch for column sums.
+template <typename T>
 struct Run {
   const bmr_csr_t* A;
+  const T* val;  // matrix values in T
   int p, nb;
   int64_t n;
   hipStream_t s;
-  Layout L;
-  char* ws;
+  int n_wg;
   DevState* st;
-  double *red, *part, *hist, *V, *M, *bench;
+  double *red, *part, *hist;
+  T *V, *M, *bench;
   size_t slot;
   std::vector<double> hpart;
 
-  double* Vslot(int64_t k) { return V + (size_t)(k % 3) * slot; }
+  T* Vslot(int64_t k) { return V + (size_t)(k % 3) * slot; }
 
   // Column sums of k_coldots, summed on the host in workgroup order.
-  int coldots(const double* Y, int ldy, int yc, const double* X, int ldx, int m, double* out) {
+  template <typename U>
+  int coldots(const U* Y, int ldy, int yc, const U* X, int ldx, int m, double* out) {
     const int g = coldots_grid(n);
-    HIP_TRY(launch_coldots(Y, ldy, yc, X, ldx, m, n, part, g, s));
+    HIP_TRY(launch_coldots<U>(Y, ldy, yc, X, ldx, m, n, part, g, s));
     hpart.resize((size_t)g * (m + 1));
     HIP_TRY(hipMemcpyAsync(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -71,11 +88,11 @@ struct Run {
     }
     return 0;
   }
-  int colop(double* D, int ldd, int dc, const double* S, int lds, int sc, const double* X, int ldx, int m,
-            const double* coef, double div) {
+  int colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m, const double* coef,
+            double div) {
     ColCoef cc;
     for (int r = 0; r < MAXP; ++r) cc.c[r] = (r < m) ? coef[r] : 0.0;
-    HIP_TRY(launch_colop(D, ldd, dc, S, lds, sc, X, ldx, m, cc, div, n, s));
+    HIP_TRY(launch_colop<T>(D, ldd, dc, S, lds, sc, X, ldx, m, cc, div, n, s));
     return 0;
   }
 };
@@ -87,7 +104,8 @@ struct Run {
 // vectors against every new column.  Coefficients go to R (stride MAXP).
 // Returns 0, or BMR_BENCH_EXHAUSTED with *lcap = the dependent column, or an
 // error.
-int column_qr(Run& r, double* D, const double* ref, double gamma, const double* bench_norm0, int* taken,
+template <typename T>
+int column_qr(Run<T>& r, T* D, const double* ref, double gamma, const double* bench_norm0, int* taken,
               int* n_replaced, double* R, int* lcap) {
   const int p = r.p, nb = r.nb;
   double c[MAXP + 1];
@@ -103,7 +121,7 @@ int column_qr(Run& r, double* D, const double* ref, double gamma, const double* 
         if (e) return e;
       }
     }
-    int e = r.coldots(D, p, l, nullptr, 0, 0, c);
+    int e = r.coldots(D, p, l, (const T*)nullptr, 0, 0, c);
     if (e) return e;
     const double eta = sqrt(c[0]);
     if (!isfinite(eta)) return BMR_NONFINITE;
@@ -112,7 +130,7 @@ int column_qr(Run& r, double* D, const double* ref, double gamma, const double* 
       bool ok = *taken < nb;
       double gn = 0.0;
       if (ok) {
-        e = r.coldots(r.bench, nb, *taken, nullptr, 0, 0, c);
+        e = r.coldots(r.bench, nb, *taken, (const T*)nullptr, 0, 0, c);
         if (e) return e;
         gn = sqrt(c[0]);
         ok = gn > gamma * bench_norm0[*taken];
@@ -148,7 +166,9 @@ int column_qr(Run& r, double* D, const double* ref, double gamma, const double* 
 
 }  // namespace
 
-Layout layout_for(int64_t n, int p, int nb, int64_t hist_cap) {
+Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision) {
+  const bool mixed = precision == BMR_PREC_MIXED;
+  const size_t esz = mixed ? sizeof(float) : sizeof(double);
   Layout L{};
   L.n_wg = pass1_grid(n, p);
   size_t off = 0;
@@ -161,14 +181,22 @@ Layout layout_for(int64_t n, int p, int nb, int64_t hist_cap) {
   L.off_part = off;
   off = align256(off + sizeof(double) * part);
   L.off_hist = off;
-  off = align256(off + sizeof(double) * (size_t)hist_cap * p);
+  off = align256(off + (mixed ? 0 : sizeof(double) * (size_t)hist_cap * p));
   const size_t se = slot_elems(n, p);
   L.off_V = off;
-  off = align256(off + sizeof(double) * 3 * se);
+  off = align256(off + esz * 3 * se);
   L.off_M = off;
-  off = align256(off + sizeof(double) * 3 * se);
+  off = align256(off + esz * 3 * se);
   L.off_bench = off;
-  off = align256(off + sizeof(double) * (size_t)n * nb);
+  off = align256(off + esz * (size_t)n * nb);
+  if (mixed) {
+    L.off_val32 = off;
+    off = align256(off + sizeof(float) * (size_t)nnz);
+    L.off_D = off;
+    off = align256(off + sizeof(float) * (size_t)n * p);
+    L.off_R = off;
+    off = align256(off + sizeof(double) * (size_t)n * p);
+  }
   L.total = off;
   return L;
 }
@@ -181,13 +209,17 @@ namespace {
 
 bool opts_valid(const bmr_opts_t& o) {
   return o.tol > 0.0 && isfinite(o.tol) && o.max_iter >= 1 && o.gamma >= 0.0 && isfinite(o.gamma) &&
-         o.n_bench >= 0 && o.n_bench <= BMR_MAX_BENCH && o.hist_cap >= 0 && o.poll_every >= 0;
+         o.n_bench >= 0 && o.n_bench <= BMR_MAX_BENCH && o.hist_cap >= 0 && o.poll_every >= 0 &&
+         (o.precision == BMR_PREC_FP64 || o.precision == BMR_PREC_MIXED) &&
+         (o.precision == BMR_PREC_FP64 || (o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_refine >= 1));
 }
 
 bool csr_valid(const bmr_csr_t* A) {
   return A && A->n >= 1 && A->n < (int64_t(1) << 31) && A->nnz >= 0 && A->nnz < (int64_t(1) << 31) &&
          A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val));
 }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Two pinned status records per host thread, reused by every solve of that
 // thread (allocated once, never freed).
@@ -201,14 +233,34 @@ Ctl* pinned_ctl() {
   return buf;
 }
 
-int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stats_t* stats, double* res_hist) {
+// Parameters and results of one run of the block-iteration driver.
+struct CoreParams {
+  double tol, gamma, tau_fb;
+  int64_t max_iter, hist_cap;
+  uint64_t seed;
+  int poll_every;
+  bool prof;
+  const double* beta_stop;  // per-column scale of the stopping test, or NULL for ||b_i||
+};
+struct CoreOut {
+  int64_t j = 0, k = 0;
+  int n_replaced = 0, n_explicit = 0;
+  double rho[MAXP] = {};
+  double tk[4] = {0, 0, 0, 0};  // summed kernel times over n_prof block iterations
+  int64_t n_prof = 0;
+};
+
+// Solve A X = B (X_0 = 0) with n-length data in T.  B is FP64 (the caller's
+// right-hand side, or the residual of a refinement cycle).
+template <typename T>
+int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& out, double* res_hist) {
   const int p = r.p, nb = r.nb;
   const int64_t n = r.n;
   // ---- set-up -------------------------------------------------------------
-  HIP_TRY(launch_fill(r.V, 3 * r.slot, 0.0, r.s));
-  HIP_TRY(launch_fill(r.M, 3 * r.slot, 0.0, r.s));
-  HIP_TRY(launch_fill(X, (size_t)n * p, 0.0, r.s));
-  HIP_TRY(launch_bench_init(r.bench, n, nb, o.seed, r.s));
+  HIP_TRY(launch_fill<T>(r.V, 3 * r.slot, T(0), r.s));
+  HIP_TRY(launch_fill<T>(r.M, 3 * r.slot, T(0), r.s));
+  HIP_TRY(launch_fill<T>(X, (size_t)n * p, T(0), r.s));
+  HIP_TRY(launch_bench_init<T>(r.bench, n, nb, o.seed, r.s));
 
   DevState* hs = new DevState();
   struct Guard {
@@ -224,41 +276,43 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
   hs->hist_cap = o.hist_cap;
   hs->tol = o.tol;
   hs->gamma = o.gamma;
-  hs->tau_fb = TAU_FB;
+  hs->tau_fb = o.tau_fb;
   hs->lcap = p;
   hs->k = 1;
 
   double c[MAXP + 1];
+  double bnorm[MAXP];
   for (int i = 0; i < p; ++i) {
-    TRY(r.coldots(B, p, i, nullptr, 0, 0, c));
-    hs->beta[i] = sqrt(c[0]);
-    if (!isfinite(hs->beta[i])) return BMR_NONFINITE;
+    TRY(r.coldots(B, p, i, (const double*)nullptr, 0, 0, c));
+    bnorm[i] = sqrt(c[0]);
+    if (!isfinite(bnorm[i])) return BMR_NONFINITE;
+    hs->beta[i] = o.beta_stop ? o.beta_stop[i] : bnorm[i];
   }
   for (int b = 0; b < nb; ++b) {
-    TRY(r.coldots(r.bench, nb, b, nullptr, 0, 0, c));
+    TRY(r.coldots(r.bench, nb, b, (const T*)nullptr, 0, 0, c));
     hs->bench_norm0[b] = sqrt(c[0]);
   }
-  // initial QR of F_0 = B into V_1 (slot 1): copy, then column-wise CGS2
-  double* V1 = r.Vslot(1);
-  for (int i = 0; i < p; ++i) TRY(r.colop(V1, p, i, B, p, i, nullptr, 0, 0, nullptr, 1.0));
+  auto finish = [&](int64_t j, int64_t kblocks, const double* rho) {
+    out.j = j;
+    out.k = kblocks;
+    out.n_replaced = hs->n_replaced;
+    out.n_explicit = hs->n_explicit;
+    for (int i = 0; i < MAXP; ++i) out.rho[i] = (i < p && rho) ? rho[i] : 0.0;
+  };
+  // initial QR of F_0 = B into V_1 (slot 1): copy (rounded to T), then column-wise CGS2
+  T* V1 = r.Vslot(1);
+  if constexpr (sizeof(T) == sizeof(double)) {
+    HIP_TRY(launch_copy(B, (double*)V1, (size_t)n * p, r.s));
+  } else {
+    HIP_TRY(launch_to_f32(B, V1, (size_t)n * p, r.s));
+  }
   double S[MAXP * MAXP];
   int lcap = p;
-  int qr = column_qr(r, V1, hs->beta, o.gamma, hs->bench_norm0, &hs->taken, &hs->n_replaced, S, &lcap);
-  auto finish_stats = [&](int status, int64_t j, int64_t kblocks, const double* rho) {
-    if (stats) {
-      stats->status = status;
-      stats->n_replaced = hs->n_replaced;
-      stats->band_iters = j;
-      stats->block_iters = kblocks;
-      stats->n_explicit_qr = hs->n_explicit;
-      stats->p = p;
-      for (int i = 0; i < BMR_MAX_P; ++i) stats->res_rec[i] = (i < p && rho) ? rho[i] : 0.0;
-    }
-  };
+  int qr = column_qr(r, V1, bnorm, o.gamma, hs->bench_norm0, &hs->taken, &hs->n_replaced, S, &lcap);
   if (qr == BMR_BENCH_EXHAUSTED) {
     double one[MAXP];
     for (int i = 0; i < p; ++i) one[i] = hs->beta[i] > 0 ? 1.0 : 0.0;
-    finish_stats(BMR_BENCH_EXHAUSTED, 0, 0, one);
+    finish(0, 0, one);
     return BMR_BENCH_EXHAUSTED;
   }
   if (qr) return qr;
@@ -274,7 +328,7 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
     worst = std::max(worst, hs->rho[cidx]);
   }
   if (worst < o.tol) {
-    finish_stats(BMR_CONVERGED, 0, 0, hs->rho);
+    finish(0, 0, hs->rho);
     return BMR_CONVERGED;
   }
   HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
@@ -294,7 +348,7 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
   } evg{ev};
   int batch = o.poll_every;
   if (batch <= 0) batch = ((double)n * p < 2e6) ? 32 : 8;
-  const bool prof = (o.flags & BMR_FLAG_PROFILE) != 0;
+  const bool prof = o.prof;
   if (prof) batch = 1;
   hipEvent_t pev[2][5];
   if (prof)
@@ -309,16 +363,14 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
           for (int b = 0; b < 5; ++b) (void)hipEventDestroy(e[a][b]);
     }
   } pevg{pev, prof};
-  double tk[4] = {0, 0, 0, 0};
-  int64_t nprof = 0;
   auto collect = [&](int slot) -> int {  // add the timings of the iteration in `slot`
     if (!prof) return 0;
     for (int q = 0; q < 4; ++q) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, pev[slot][q], pev[slot][q + 1]));
-      tk[q] += ms;
+      out.tk[q] += ms;
     }
-    ++nprof;
+    ++out.n_prof;
     return 0;
   };
 
@@ -326,13 +378,13 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
   auto enq = [&](int slot) -> int {
     for (int q = 0; q < batch; ++q) {
       if (prof) HIP_TRY(hipEventRecord(pev[slot][0], r.s));
-      HIP_TRY(launch_pass1(r.p, *r.A, r.V, r.slot, r.bench, r.part, r.L.n_wg, r.st, r.s));
+      HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][1], r.s));
-      HIP_TRY(launch_reduce(r.part, r.L.n_wg, n_entries(r.p, r.nb), r.red, r.st, 1, r.s));
+      HIP_TRY(launch_reduce(r.part, r.n_wg, n_entries(r.p, r.nb), r.red, r.st, 1, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][2], r.s));
       HIP_TRY(launch_band(r.p, 0, r.red, r.hist, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][3], r.s));
-      HIP_TRY(launch_pass2(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
+      HIP_TRY(launch_pass2<T>(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][4], r.s));
     }
     HIP_TRY(hipMemcpyAsync(&pin[slot], r.st, sizeof(Ctl), hipMemcpyDeviceToHost, r.s));
@@ -360,8 +412,8 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
     const int64_t k = ctl.k;
     HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
     HIP_TRY(hipStreamSynchronize(r.s));
-    double* Wn = r.Vslot(k + 1);
-    const double* Vk = r.Vslot(k);
+    T* Wn = r.Vslot(k + 1);
+    const T* Vk = r.Vslot(k);
     for (int l = 0; l < p; ++l) {
       double a[MAXP];
       for (int q = 0; q < p; ++q) a[q] = hs->Ak[q * MAXP + l];
@@ -381,7 +433,7 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
     hs->reason = REASON_NONE;
     HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
     HIP_TRY(launch_band(r.p, 1, r.red, r.hist, r.st, r.s));
-    HIP_TRY(launch_pass2(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
+    HIP_TRY(launch_pass2<T>(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
     HIP_TRY(hipStreamSynchronize(r.s));
   }
   HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
@@ -392,10 +444,143 @@ int solve_impl(Run& r, const double* B, double* X, const bmr_opts_t& o, bmr_stat
       HIP_TRY(hipMemcpy(res_hist, r.hist, sizeof(double) * (size_t)rows * p, hipMemcpyDeviceToHost));
   }
   const int status = hs->status == STATUS_RUNNING ? BMR_HIP_ERROR : hs->status;
-  finish_stats(status, hs->j, hs->k, hs->rho);
+  finish(hs->j, hs->k, hs->rho);
+  return status;
+}
+
+// Point the run's fields into the workspace.
+template <typename T>
+void bind(Run<T>& r, const bmr_csr_t* A, const T* val, int p, int nb, hipStream_t s, char* ws, const Layout& L) {
+  r.A = A;
+  r.val = val;
+  r.p = p;
+  r.nb = nb;
+  r.n = A->n;
+  r.s = s;
+  r.n_wg = L.n_wg;
+  r.st = (DevState*)(ws + L.off_state);
+  r.red = (double*)(ws + L.off_red);
+  r.part = (double*)(ws + L.off_part);
+  r.hist = (double*)(ws + L.off_hist);
+  r.V = (T*)(ws + L.off_V);
+  r.M = (T*)(ws + L.off_M);
+  r.bench = (T*)(ws + L.off_bench);
+  r.slot = slot_elems(A->n, p);
+}
+
+// R = B - A X (R may be NULL) and the column norms, summed on the host in
+// workgroup order.  part: p * n_wg doubles of device scratch.
+int residual_norms(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* part, int n_wg,
+                   hipStream_t s, double* norms) {
+  HIP_TRY(launch_residual(p, *A, B, X, R, part, n_wg, s));
+  std::vector<double> h((size_t)p * n_wg);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < p; ++c) {
+    double t = 0.0;
+    for (int w = 0; w < n_wg; ++w) t += h[(size_t)c * n_wg + w];
+    norms[c] = sqrt(t);
+  }
+  return 0;
+}
+
+void fill_stats(bmr_stats_t* stats, int status, int p, const CoreOut& o) {
+  if (!stats) return;
+  memset(stats, 0, sizeof(*stats));
+  stats->status = status;
+  stats->n_replaced = o.n_replaced;
+  stats->band_iters = o.j;
+  stats->block_iters = o.k;
+  stats->n_explicit_qr = o.n_explicit;
+  stats->p = p;
+  for (int i = 0; i < BMR_MAX_P; ++i) stats->res_rec[i] = i < p ? o.rho[i] : 0.0;
+  for (int q = 0; q < 4; ++q) stats->t_kernel_ms[q] = o.n_prof ? o.tk[q] / o.n_prof : 0.0;
+  stats->n_profiled = o.n_prof;
+}
+
+int solve_fp64(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_opts_t& o, char* ws,
+               const Layout& L, hipStream_t s, bmr_stats_t* stats, double* res_hist) {
+  Run<double> r{};
+  bind(r, A, A->val, p, o.n_bench, s, ws, L);
+  CoreParams cp{o.tol, o.gamma, TAU_FB, o.max_iter, o.hist_cap, o.seed, o.poll_every,
+                (o.flags & BMR_FLAG_PROFILE) != 0, nullptr};
+  CoreOut out;
+  const int status = solve_core<double>(r, B, X, cp, out, res_hist);
+  if (status >= 0) fill_stats(stats, status, p, out);
+  return status;
+}
+
+// FP64 iterative refinement around the FP32 driver:
+//   R = B - A X (FP64); stop when every ||r_i|| / ||b_i|| < tol;
+//   solve A D = R in FP32 until each column's recurrence residual is below
+//   max(inner_tol * ||r_i||, tol * ||b_i|| / 2);  X += D (FP64).
+int solve_mixed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_opts_t& o, char* ws,
+                const Layout& L, hipStream_t s, bmr_stats_t* stats, double* res_hist) {
+  const int64_t n = A->n;
+  float* val32 = (float*)(ws + L.off_val32);
+  float* D = (float*)(ws + L.off_D);
+  double* R = (double*)(ws + L.off_R);
+  double* part = (double*)(ws + L.off_part);
+  Run<float> r{};
+  bind(r, A, (const float*)val32, p, o.n_bench, s, ws, L);
+  HIP_TRY(launch_to_f32(A->val, val32, (size_t)A->nnz, s));
+  HIP_TRY(launch_fill<double>(X, (size_t)n * p, 0.0, s));
+
+  double beta[MAXP], rn[MAXP], stop[MAXP], rel[MAXP];
+  TRY(residual_norms(A, B, X, p, R, part, L.n_wg, s, beta));  // X = 0: R = B
+  for (int i = 0; i < p; ++i) {
+    if (!isfinite(beta[i])) return BMR_NONFINITE;
+    rn[i] = beta[i];
+  }
+  CoreOut tot;
+  int status = BMR_MAX_ITER, cycles = 0;
+  double prev_worst = HUGE_VAL;
+  for (;;) {
+    double worst = 0.0;
+    for (int i = 0; i < p; ++i) {
+      rel[i] = beta[i] > 0 ? rn[i] / beta[i] : 0.0;
+      if (!isfinite(rel[i])) return BMR_NONFINITE;
+      worst = std::max(worst, rel[i]);
+    }
+    if (cycles > 0 && res_hist && cycles <= o.hist_cap)
+      for (int i = 0; i < p; ++i) res_hist[(size_t)(cycles - 1) * p + i] = rel[i];
+    if (worst < o.tol) {
+      status = BMR_CONVERGED;
+      break;
+    }
+    if (cycles > 0 && worst > 0.5 * prev_worst) {
+      status = BMR_STAGNATED;
+      break;
+    }
+    if (cycles >= o.max_refine || tot.j >= o.max_iter) {
+      status = BMR_MAX_ITER;
+      break;
+    }
+    if (status == BMR_BENCH_EXHAUSTED) break;
+    prev_worst = worst;
+    for (int i = 0; i < p; ++i) stop[i] = std::max(rn[i], 0.5 * o.tol * beta[i] / o.inner_tol);
+    CoreParams cp{o.inner_tol, std::max(o.gamma, GAMMA_F32), TAU_FB_F32, o.max_iter - tot.j, 0, o.seed,
+                  o.poll_every, (o.flags & BMR_FLAG_PROFILE) != 0, stop};
+    CoreOut out;
+    const int st = solve_core<float>(r, R, D, cp, out, nullptr);
+    if (st < 0) return st;
+    ++cycles;
+    tot.j += out.j;
+    tot.k += out.k;
+    tot.n_replaced += out.n_replaced;
+    tot.n_explicit += out.n_explicit;
+    for (int q = 0; q < 4; ++q) tot.tk[q] += out.tk[q];
+    tot.n_prof += out.n_prof;
+    HIP_TRY(launch_add_f32(X, D, (size_t)n * p, s));
+    TRY(residual_norms(A, B, X, p, R, part, L.n_wg, s, rn));
+    status = st == BMR_BENCH_EXHAUSTED ? BMR_BENCH_EXHAUSTED : BMR_MAX_ITER;
+  }
+  for (int i = 0; i < p; ++i) tot.rho[i] = rel[i];
+  fill_stats(stats, status, p, tot);
   if (stats) {
-    for (int q = 0; q < 4; ++q) stats->t_kernel_ms[q] = nprof ? tk[q] / nprof : 0.0;
-    stats->n_profiled = nprof;
+    stats->precision = BMR_PREC_MIXED;
+    stats->n_refine = cycles;
+    for (int i = 0; i < p; ++i) stats->res_true[i] = rel[i];
   }
   return status;
 }
@@ -411,6 +596,7 @@ const char* bmr_status_string(int status) {
     case BMR_CONVERGED: return "converged";
     case BMR_MAX_ITER: return "maximum iterations reached";
     case BMR_BENCH_EXHAUSTED: return "substitute bench exhausted";
+    case BMR_STAGNATED: return "refinement stagnated";
     case BMR_INVALID_ARG: return "invalid argument";
     case BMR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case BMR_HIP_ERROR: return "HIP runtime error";
@@ -422,6 +608,7 @@ const char* bmr_status_string(int status) {
 
 void bmr_default_opts(bmr_opts_t* o) {
   if (!o) return;
+  memset(o, 0, sizeof(*o));
   o->tol = 1e-8;
   o->max_iter = 10000;
   o->gamma = 1e-10;
@@ -430,15 +617,17 @@ void bmr_default_opts(bmr_opts_t* o) {
   o->seed = 0;
   o->hist_cap = 0;
   o->flags = 0;
-  o->_reserved = 0;
+  o->precision = BMR_PREC_FP64;
+  o->inner_tol = 1e-6;
+  o->max_refine = 30;
 }
 
-int bmr_workspace_bytes(int64_t n, int p, const bmr_opts_t* opts, size_t* bytes) {
+int bmr_workspace_bytes(int64_t n, int64_t nnz, int p, const bmr_opts_t* opts, size_t* bytes) {
   bmr_opts_t o;
   bmr_default_opts(&o);
   if (opts) o = *opts;
-  if (!bytes || n < 1 || p < 1 || p > BMR_MAX_P || !opts_valid(o)) return BMR_INVALID_ARG;
-  *bytes = layout_for(n, p, o.n_bench, o.hist_cap).total;
+  if (!bytes || n < 1 || nnz < 0 || p < 1 || p > BMR_MAX_P || !opts_valid(o)) return BMR_INVALID_ARG;
+  *bytes = layout_for(n, nnz, p, o.n_bench, o.hist_cap, o.precision).total;
   return BMR_CONVERGED;
 }
 
@@ -448,29 +637,16 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
   bmr_default_opts(&o);
   if (opts) o = *opts;
   if (!csr_valid(A) || !B || !X || !workspace || p < 1 || p > BMR_MAX_P || !opts_valid(o)) return BMR_INVALID_ARG;
-  if (((uintptr_t)workspace) % 256 != 0) return BMR_INVALID_ARG;
-  Run r{};
-  r.A = A;
-  r.p = p;
-  r.nb = o.n_bench;
-  r.n = A->n;
-  r.s = stream;
-  r.L = layout_for(A->n, p, o.n_bench, o.hist_cap);
-  if (workspace_bytes < r.L.total) return BMR_WORKSPACE_TOO_SMALL;
-  r.ws = (char*)workspace;
-  r.st = (DevState*)(r.ws + r.L.off_state);
-  r.red = (double*)(r.ws + r.L.off_red);
-  r.part = (double*)(r.ws + r.L.off_part);
-  r.hist = (double*)(r.ws + r.L.off_hist);
-  r.V = (double*)(r.ws + r.L.off_V);
-  r.M = (double*)(r.ws + r.L.off_M);
-  r.bench = (double*)(r.ws + r.L.off_bench);
-  r.slot = slot_elems(A->n, p);
+  if (((uintptr_t)workspace) % 256 != 0 || !aligned16(B) || !aligned16(X)) return BMR_INVALID_ARG;
+  const Layout L = layout_for(A->n, A->nnz, p, o.n_bench, o.hist_cap, o.precision);
+  if (workspace_bytes < L.total) return BMR_WORKSPACE_TOO_SMALL;
   hipEvent_t t0, t1;
   if (hipEventCreate(&t0) != hipSuccess) return BMR_HIP_ERROR;
   if (hipEventCreate(&t1) != hipSuccess) return BMR_HIP_ERROR;
   (void)hipEventRecord(t0, stream);
-  int status = solve_impl(r, B, X, o, stats, res_hist);
+  const int status = o.precision == BMR_PREC_MIXED
+                         ? solve_mixed(A, B, X, p, o, (char*)workspace, L, stream, stats, res_hist)
+                         : solve_fp64(A, B, X, p, o, (char*)workspace, L, stream, stats, res_hist);
   (void)hipEventRecord(t1, stream);
   (void)hipEventSynchronize(t1);
   float ms = 0.f;
@@ -483,36 +659,36 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
       stats->status = status;
       stats->p = p;
     }
+    stats->precision = o.precision;
     stats->time_ms = ms;
   }
   return status;
 }
 
 int bmr_spmm(const bmr_csr_t* A, const double* V, double* W, int p, hipStream_t stream) {
-  if (!csr_valid(A) || !V || !W || V == W || p < 1 || p > BMR_MAX_P) return BMR_INVALID_ARG;
-  return launch_spmm(p, *A, V, W, stream) == hipSuccess ? BMR_CONVERGED : BMR_HIP_ERROR;
+  if (!csr_valid(A) || !V || !W || V == W || p < 1 || p > BMR_MAX_P || !aligned16(V) || !aligned16(W))
+    return BMR_INVALID_ARG;
+  return launch_spmm<double>(p, *A, A->val, V, W, stream) == hipSuccess ? BMR_CONVERGED : BMR_HIP_ERROR;
+}
+
+int bmr_spmm_f32(const bmr_csr_t* A, const float* val32, const float* V, float* W, int p, hipStream_t stream) {
+  if (!csr_valid(A) || (A->nnz > 0 && !val32) || !V || !W || V == W || p < 1 || p > BMR_MAX_P || !aligned16(V) ||
+      !aligned16(W))
+    return BMR_INVALID_ARG;
+  return launch_spmm<float>(p, *A, val32, V, W, stream) == hipSuccess ? BMR_CONVERGED : BMR_HIP_ERROR;
 }
 
 int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* norms,
                  void* workspace, size_t workspace_bytes, hipStream_t stream) {
   if (!csr_valid(A) || !B || !X || !norms || !workspace || p < 1 || p > BMR_MAX_P) return BMR_INVALID_ARG;
+  if (!aligned16(X)) return BMR_INVALID_ARG;
   bmr_opts_t o;
   bmr_default_opts(&o);
-  const Layout L = layout_for(A->n, p, o.n_bench, 0);
+  const Layout L = layout_for(A->n, 0, p, o.n_bench, 0, BMR_PREC_FP64);
   const size_t need = L.off_part + sizeof(double) * (size_t)p * L.n_wg;
   if (workspace_bytes < need) return BMR_WORKSPACE_TOO_SMALL;
   double* part = (double*)((char*)workspace + L.off_part);
-  if (launch_residual(p, *A, B, X, R, part, L.n_wg, stream) != hipSuccess) return BMR_HIP_ERROR;
-  std::vector<double> h((size_t)p * L.n_wg);
-  if (hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream) != hipSuccess)
-    return BMR_HIP_ERROR;
-  if (hipStreamSynchronize(stream) != hipSuccess) return BMR_HIP_ERROR;
-  for (int c = 0; c < p; ++c) {
-    double t = 0.0;
-    for (int w = 0; w < L.n_wg; ++w) t += h[(size_t)c * L.n_wg + w];
-    norms[c] = sqrt(t);
-  }
-  return BMR_CONVERGED;
+  return residual_norms(A, B, X, p, R, part, L.n_wg, stream, norms) == 0 ? BMR_CONVERGED : BMR_HIP_ERROR;
 }
 
 }  // extern "C"

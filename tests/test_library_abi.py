@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "bmr.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bmr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(bmr_[a-z_0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -32,9 +32,9 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.bmr_version() == 10000
-    for code, word in [(0, "converged"), (1, "maximum"), (2, "bench"), (-1, "invalid"), (-2, "workspace"),
-                       (-3, "HIP"), (-4, "non-finite"), (-5, "singular")]:
+    assert lib.bmr_version() == 10100
+    for code, word in [(0, "converged"), (1, "maximum"), (2, "bench"), (3, "stagnated"), (-1, "invalid"),
+                       (-2, "workspace"), (-3, "HIP"), (-4, "non-finite"), (-5, "singular")]:
         assert word in bmr.status_string(code)
 
 
@@ -42,6 +42,8 @@ def test_default_opts(lib):
     o = bmr._Opts()
     lib.bmr_default_opts(ctypes.byref(o))
     assert (o.tol, o.max_iter, o.gamma, o.n_bench, o.seed, o.hist_cap, o.flags) == (1e-8, 10000, 1e-10, 2, 0, 0, 0)
+    assert (o.precision, o.inner_tol, o.max_refine) == (bmr.PREC_FP64, 1e-6, 30)
+    assert ctypes.sizeof(bmr._Opts) == 72 and ctypes.sizeof(bmr._Stats) == 344  # sizeof in C
 
 
 def test_workspace_bytes(lib):
@@ -50,35 +52,63 @@ def test_workspace_bytes(lib):
     blocks = 6 * n * p * 8 + 2 * n * 8  # V and M rings + bench
     assert blocks < ws < blocks + (16 << 20)
     assert bmr.workspace_bytes(n, p, hist_cap=1000) >= ws + 1000 * p * 8
+    # mixed precision: FP32 rings and bench, FP32 matrix values, FP32 D, FP64 R
+    nnz = 14581760
+    wm = bmr.workspace_bytes(n, p, nnz=nnz, precision="mixed")
+    mixed = 6 * n * p * 4 + 2 * n * 4 + nnz * 4 + n * p * 4 + n * p * 8
+    assert mixed < wm < mixed + (16 << 20)
     out = ctypes.c_size_t()
-    for bad in [(0, 8), (10, 0), (10, 17)]:
-        assert lib.bmr_workspace_bytes(bad[0], bad[1], None, ctypes.byref(out)) == bmr.INVALID_ARG
+    for bad in [(0, 0, 8), (10, 0, 0), (10, 0, 17), (10, -1, 4)]:
+        assert lib.bmr_workspace_bytes(bad[0], bad[1], bad[2], None, ctypes.byref(out)) == bmr.INVALID_ARG
+    o = bmr._Opts()
+    for field, value in [("precision", 2), ("inner_tol", 0.0), ("inner_tol", 1.0), ("max_refine", 0)]:
+        lib.bmr_default_opts(ctypes.byref(o))
+        o.precision = bmr.PREC_MIXED
+        setattr(o, field, value)
+        assert lib.bmr_workspace_bytes(10, 28, 4, ctypes.byref(o), ctypes.byref(out)) == bmr.INVALID_ARG
 
 
 def test_invalid_arguments_rejected_on_host(lib):
-    A = bmr._Csr(10, 28, 1, 1, 1)
+    # the pointers are never dereferenced: every call below fails its host checks
+    A = bmr._Csr(10, 28, 256, 256, 256)
     o = bmr._Opts()
     lib.bmr_default_opts(ctypes.byref(o))
     st = bmr._Stats()
+    B, X = 1024, 2048
     # null B / X / workspace, bad p, bad tol: rejected before any device work
-    assert lib.bmr_solve(ctypes.byref(A), None, 1, 4, ctypes.byref(o), 256, 1 << 20, None, ctypes.byref(st),
+    assert lib.bmr_solve(ctypes.byref(A), None, X, 4, ctypes.byref(o), 256, 1 << 20, None, ctypes.byref(st),
                          None) == bmr.INVALID_ARG
-    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 0, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
-    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 17, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 0, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 17, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
     o.tol = 0.0
-    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
     lib.bmr_default_opts(ctypes.byref(o))
     o.n_bench = 5
-    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
     lib.bmr_default_opts(ctypes.byref(o))
-    # unaligned and too small workspaces
-    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 257, 1 << 20, None, None, None) == bmr.INVALID_ARG
-    assert lib.bmr_solve(ctypes.byref(A), 1, 1, 4, ctypes.byref(o), 256, 16, None, None,
+    o.precision = bmr.PREC_MIXED
+    o.inner_tol = 2.0
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 4, ctypes.byref(o), 256, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    lib.bmr_default_opts(ctypes.byref(o))
+    # misaligned blocks, unaligned and too small workspaces
+    assert lib.bmr_solve(ctypes.byref(A), B + 8, X, 4, ctypes.byref(o), 256, 1 << 20, None, None,
+                         None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X + 8, 4, ctypes.byref(o), 256, 1 << 20, None, None,
+                         None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 4, ctypes.byref(o), 257, 1 << 20, None, None, None) == bmr.INVALID_ARG
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 4, ctypes.byref(o), 256, 16, None, None,
                          None) == bmr.WORKSPACE_TOO_SMALL
-    assert lib.bmr_spmm(ctypes.byref(A), 1, 1, 0, None) == bmr.INVALID_ARG
-    assert lib.bmr_spmm(ctypes.byref(A), 1, 1, 4, None) == bmr.INVALID_ARG  # V aliases W
-    bad = bmr._Csr(0, 0, 1, 1, 1)
-    assert lib.bmr_spmm(ctypes.byref(bad), 1, 2, 4, None) == bmr.INVALID_ARG
+    o.precision = bmr.PREC_MIXED
+    assert lib.bmr_solve(ctypes.byref(A), B, X, 4, ctypes.byref(o), 256, 16, None, None,
+                         None) == bmr.WORKSPACE_TOO_SMALL
+    assert lib.bmr_spmm(ctypes.byref(A), B, X, 0, None) == bmr.INVALID_ARG
+    assert lib.bmr_spmm(ctypes.byref(A), B, B, 4, None) == bmr.INVALID_ARG  # V aliases W
+    assert lib.bmr_spmm(ctypes.byref(A), B + 8, X, 4, None) == bmr.INVALID_ARG
+    bad = bmr._Csr(0, 0, 256, 256, 256)
+    assert lib.bmr_spmm(ctypes.byref(bad), B, X, 4, None) == bmr.INVALID_ARG
+    assert lib.bmr_spmm_f32(ctypes.byref(A), None, B, X, 4, None) == bmr.INVALID_ARG  # no FP32 values
+    assert lib.bmr_spmm_f32(ctypes.byref(A), 512, B, B, 4, None) == bmr.INVALID_ARG
+    assert lib.bmr_spmm_f32(ctypes.byref(A), 512, B, X, 17, None) == bmr.INVALID_ARG
 
 
 def test_no_cpu_fallback_in_product_path():
