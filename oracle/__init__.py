@@ -16,7 +16,9 @@ Pins (tests that tie this code to something other than itself) live in
 ``tests/test_oracle_*.py``: a dense direct solve, the least-squares definition
 over a brute-force band basis, classical MINRES at p = 1, the band Arnoldi
 relation, the worked replacement example of Section 5.1, the C_{pxp} layout
-of Section 7 and the dependence demonstration of Section 8.
+of Section 7 and the dependence demonstration of Section 8.  The adjoint
+gradients of ``adjoint.py`` (an extension, not in the paper) are pinned by
+central finite differences of dense direct solves.
 """
 from .block_minres import (  # noqa: F401
     CONVERGED,
@@ -27,3 +29,4 @@ from .block_minres import (  # noqa: F401
     solve,
 )
 from .rng import bench_vector, splitmix64  # noqa: F401
+from .adjoint import Grad, loss_grad, pattern_grad  # noqa: F401

@@ -12,6 +12,10 @@ from .gen import (  # noqa: F401
     rhs_normal,
     rhs_stress,
     rhs_e1_ae1,
+    diag_positions,
+    with_diagonal_shift,
+    ThetaProblem,
+    theta_problem,
     WORKLOADS,
     workload,
 )

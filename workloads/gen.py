@@ -145,6 +145,53 @@ def rhs_e1_ae1(A: Csr, extra: int = 0, seed: int = 0) -> np.ndarray:
     return np.ascontiguousarray(np.stack(cols, axis=1))
 
 
+def diag_positions(A: Csr) -> np.ndarray:
+    """Index into A.data of the diagonal entry of every row (each row must
+    store its diagonal)."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.indptr))
+    pos = np.nonzero(A.indices == rows)[0]
+    if pos.size != A.n:
+        raise ValueError("every row must store its diagonal")
+    return pos
+
+
+def with_diagonal_shift(A: Csr, d) -> Csr:
+    """A + diag(d) on A's pattern (d a scalar or an n-vector)."""
+    data = A.data.copy()
+    data[diag_positions(A)] += np.broadcast_to(np.asarray(d, dtype=np.float64), (A.n,))
+    return Csr(A.n, A.indptr, A.indices, data)
+
+
+@dataclass(frozen=True)
+class ThetaProblem:
+    """Parametrised system A(theta, sigma) X = B with loss sum(W * X):
+    A(theta, sigma) = L + diag(theta) - sigma I for the unshifted grid
+    Laplacian L."""
+
+    L: Csr
+    theta: np.ndarray
+    sigma: float
+    B: np.ndarray
+    W: np.ndarray
+
+    def matrix(self, theta=None, sigma=None) -> Csr:
+        theta = self.theta if theta is None else theta
+        sigma = self.sigma if sigma is None else sigma
+        return with_diagonal_shift(self.L, np.asarray(theta) - sigma)
+
+
+def theta_problem(dims=(96, 96, 96), sigma: float = 0.3, p: int = 8, seed: int = 0,
+                  theta_range: float = 0.1) -> ThetaProblem:
+    """Differentiable-solve workload: theta ~ U(-theta_range, theta_range),
+    B and the loss weights W ~ N(0, 1), n x p."""
+    L = laplacian(dims, 0.0)
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(-theta_range, theta_range, L.n)
+    B = np.ascontiguousarray(rng.standard_normal((p, L.n)).T)
+    W = np.ascontiguousarray(rng.standard_normal((p, L.n)).T)
+    return ThetaProblem(L, theta, float(sigma), B, W)
+
+
 # Named workloads: the matrices and right-hand sides the tests and the
 # benchmark run.  ``tol``/``max_iter`` are the solve parameters.
 WORKLOADS = {
