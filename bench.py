@@ -29,14 +29,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(A, p, nb):
-    """Algorithmic bytes per launch of the two streaming kernels (binary64
-    values, int32 indices): each input and output touched once."""
+def kernel_bytes(A, p, nb, esz=8):
+    """Algorithmic bytes per launch of the two streaming kernels (esz-byte
+    values: 8 for FP64, 4 for the FP32 inner solve; int32 indices): each
+    input and output touched once."""
     n, nnz = A.n, A.nnz
-    blk = 8 * n * p
-    pass1 = 12 * nnz + 4 * (n + 1) + 3 * blk + 8 * n * nb          # A, V_k, V_{k-1}, W out, bench in
-    pass2 = 8 * blk + 16 * n * nb                                  # W, V_k, V_{k+1}, M x3, X in/out, bench
-    spmm = 12 * nnz + 4 * (n + 1) + 2 * blk                        # A, V in, W out
+    blk = esz * n * p
+    pass1 = (4 + esz) * nnz + 4 * (n + 1) + 3 * blk + esz * n * nb   # A, V_k, V_{k-1}, W out, bench in
+    pass2 = 8 * blk + 2 * esz * n * nb                               # W, V_k, V_{k+1}, M x3, X in/out, bench
+    spmm = (4 + esz) * nnz + 4 * (n + 1) + 2 * blk                   # A, V in, W out
     return {"pass1_spmm_gram": pass1, "pass2_update": pass2, "spmm": spmm}
 
 
@@ -105,6 +106,8 @@ def main():
     ap.add_argument("--spmm-reps", type=int, default=50)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for hardware byte counters)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--inner-tol", type=float, default=1e-6)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -165,30 +168,70 @@ def main():
     # launches are captured in a graph so that the host's per-call cost does
     # not pace the GPU; HIP events bracket the replay on the same stream.
     spmm = {}
-    for q in (1, 8, 16):
-        V = torch.from_numpy(rhs_normal(n, q, seed=1)).to(dev)
-        W = torch.empty_like(V)
-        for _ in range(3):
-            bmr.spmm(Ad, V, W)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            for _ in range(args.spmm_reps):
-                bmr.spmm(Ad, V, W)
-        graph.replay()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        graph.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.spmm_reps
-        del graph
-        b = kernel_bytes(A, q, 0)["spmm"]
-        spmm[f"p{q}"] = {"avg_ms": round(ms, 5), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
+    val32 = Ad.val.float()
+    for prec, esz in (("fp64", 8), ("fp32", 4)):
+        for q in (1, 8, 16):
+            dt = torch.float64 if esz == 8 else torch.float32
+            V = torch.from_numpy(rhs_normal(n, q, seed=1)).to(dev).to(dt)
+            W = torch.empty_like(V)
+
+            def op():
+                if esz == 8:
+                    bmr.spmm(Ad, V, W)
+                else:
+                    bmr.spmm_f32(Ad, val32, V, W)
+            for _ in range(3):
+                op()
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                for _ in range(args.spmm_reps):
+                    op()
+            graph.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.spmm_reps
+            del graph
+            b = kernel_bytes(A, q, 0, esz)["spmm"]
+            key = f"p{q}" if esz == 8 else f"p{q}_fp32"
+            spmm[key] = {"avg_ms": round(ms, 5), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
                          "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": b}
-        del V, W
+            del V, W
+    del val32
     log(f"[bench] spmm: {spmm}")
+
+    # mixed precision: FP32 inner block MINRES inside FP64 iterative
+    # refinement, same system and tolerance (explicit FP64 residual), then a
+    # profiled prefix for the FP32 kernels' durations
+    mixed = None
+    if not args.no_mixed:
+        Xm = torch.empty_like(Bd)
+        wsm = torch.empty(bmr.workspace_bytes(n, p, nnz=A.nnz, precision="mixed"), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, minfo = bmr.solve(Ad, Bd, tol=tol, max_iter=2 * max_iter, X=Xm, workspace=wsm, precision="mixed",
+                             inner_tol=args.inner_tol, hist_cap=64)
+        torch.cuda.synchronize()
+        mt = time.perf_counter() - t0
+        mexp = float((bmr.residual(Ad, Bd, Xm) / beta).max())
+        err_vs_fp64 = float((torch.linalg.vector_norm(Xm - X, dim=0) / torch.linalg.vector_norm(X, dim=0)).max())
+        _, mp = bmr.solve(Ad, Bd, tol=tol, max_iter=min(8 * p * 250, max_iter), workspace=wsm, precision="mixed",
+                          inner_tol=args.inner_tol, max_refine=1, profile=True)
+        mb = kernel_bytes(A, p, 2, esz=4)
+        mk = {k: {"avg_ms": round(mp.kernel_ms[k], 5),
+                  "GB/s": round(mb[k] / (mp.kernel_ms[k] * 1e-3) / 1e9, 1) if k in mb else None}
+              for k in ("pass1_spmm_gram", "reduce", "band", "pass2_update")}
+        mixed = {"value": round(mt, 6), "unit": "s", "status": minfo.status_name, "inner_tol": args.inner_tol,
+                 "cycles": minfo.n_refine, "band_iters": minfo.band_iters, "block_iters": minfo.block_iters,
+                 "res_explicit_max": mexp, "cycle_res": [float(v) for v in minfo.hist.max(axis=1)],
+                 "x_err_vs_fp64": err_vs_fp64, "ms_per_block_iter": round(1e3 * mt / max(minfo.block_iters, 1), 4),
+                 "kernels": mk}
+        log(f"[bench] mixed: {mixed}")
+        del Xm, wsm
 
     if args.copy_ref_mib:
         src = torch.empty(args.copy_ref_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
@@ -228,6 +271,7 @@ def main():
         "kernels": kernels,
         "spmm": spmm,
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
     print(json.dumps(out), flush=True)
 

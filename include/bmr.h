@@ -196,6 +196,21 @@ int bmr_spmm(const bmr_csr_t* A, const double* V, double* W, int p, hipStream_t 
  * Products and sums in binary32.  Asynchronous. */
 int bmr_spmm_f32(const bmr_csr_t* A, const float* val32, const float* V, float* W, int p, hipStream_t stream);
 
+/* Gradient of a scalar loss L(X) of the solution X = A^{-1} B with respect to
+ * the stored entries of A, given the adjoint solution Lam = A^{-1} dL/dX
+ * (computed with bmr_solve on the same A, which is symmetric).  Since
+ * dL = <Lam, dB> - <Lam X^T, dA>, the gradient restricted to A's pattern and
+ * symmetrised (the gradient with respect to symmetric perturbations supported
+ * on the pattern) is, for the stored entry e = (i, j),
+ *     grad[e] = -(Lam_i . X_j + Lam_j . X_i) / 2,
+ * where Lam_i . X_j is the dot product of row i of Lam and row j of X.  Not
+ * part of the paper: the backward pass of a differentiable solve.
+ *   Lam, X     device, n x p row-interleaved binary64.
+ *   grad       device, A->nnz doubles, in the order of A's entries.
+ * Asynchronous. */
+int bmr_pattern_grad(const bmr_csr_t* A, const double* Lam, const double* X, int p, double* grad,
+                     hipStream_t stream);
+
 /* Explicit residual R = B - A X and its column norms (the quantity the
  * stopping test of Algorithm 7.1 bounds).
  *   B, X       device, n x p row-interleaved.

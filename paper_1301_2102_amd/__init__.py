@@ -58,7 +58,7 @@ KERNEL_NAMES = ("pass1_spmm_gram", "reduce", "band", "pass2_update")
 
 
 EXPORTS = ("bmr_version", "bmr_status_string", "bmr_default_opts", "bmr_workspace_bytes", "bmr_solve",
-           "bmr_spmm", "bmr_spmm_f32", "bmr_residual")
+           "bmr_spmm", "bmr_spmm_f32", "bmr_pattern_grad", "bmr_residual")
 
 _lib = None
 
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.bmr_spmm.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp]
     lib.bmr_spmm_f32.restype = i32
     lib.bmr_spmm_f32.argtypes = [ctypes.POINTER(_Csr), vp, vp, vp, i32, vp]
+    lib.bmr_pattern_grad.restype = i32
+    lib.bmr_pattern_grad.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp, vp]
     lib.bmr_residual.restype = i32
     lib.bmr_residual.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
     _lib = lib
@@ -274,6 +276,25 @@ def spmm_f32(A: DeviceCsr, val32, V, W=None):
     if st != 0:
         raise BmrError(st, "bmr_spmm_f32")
     return W
+
+
+def pattern_grad(A: DeviceCsr, Lam, X, out=None):
+    """grad[e] = -(Lam_i . X_j + Lam_j . X_i) / 2 for every stored entry
+    e = (i, j) of A: the symmetrised gradient on A's pattern of a loss whose
+    adjoint solution is Lam (asynchronous)."""
+    import torch
+    _check_block(Lam, A.n, "Lam")
+    _check_block(X, A.n, "X")
+    if Lam.shape != X.shape:
+        raise ValueError("Lam and X must have the same shape")
+    if out is None:
+        out = torch.empty(A.nnz, dtype=torch.float64, device=X.device)
+    Ac = A._c()
+    st = load().bmr_pattern_grad(ctypes.byref(Ac), Lam.data_ptr(), X.data_ptr(), int(X.shape[1]), out.data_ptr(),
+                                 _stream_handle(X.device))
+    if st != 0:
+        raise BmrError(st, "bmr_pattern_grad")
+    return out
 
 
 def residual(A: DeviceCsr, B, X, want_R: bool = False, workspace=None):

@@ -128,5 +128,8 @@ int coldots_grid(int64_t n);
 hipError_t launch_to_f32(const double* src, float* dst, size_t count, hipStream_t s);
 hipError_t launch_add_f32(double* x, const float* d, size_t count, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s);
+// g_e = -(Lam_i . X_j + Lam_j . X_i) / 2 for every stored entry e = (i, j) of A.
+hipError_t launch_pattern_grad(int p, const bmr_csr_t& A, const double* Lam, const double* X, double* g,
+                               hipStream_t s);
 
 }  // namespace bmr

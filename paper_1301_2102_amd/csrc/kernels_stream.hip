@@ -207,6 +207,36 @@ __global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ d, s
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) x[i] += (double)d[i];
 }
 
+// Gradient of a loss of X = A^{-1} B with respect to the stored entries of A,
+// symmetrised: for entry e = (i, j), g_e = -(Lam_i . X_j + Lam_j . X_i) / 2,
+// with Lam the adjoint solution.  One lane per row i; its own rows of Lam and
+// X stay in registers, the rows j of its entries are gathered.
+template <int P>
+__global__ __launch_bounds__(WG) void k_pattern_grad(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                     const double* __restrict__ Lam, const double* __restrict__ X,
+                                                     double* __restrict__ g, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += stride) {
+    double li[P], xi[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      li[c] = Lam[i * P + c];
+      xi[c] = X[i * P + c];
+    }
+    const int s = rp[i], e = rp[i + 1];
+    for (int q = s; q < e; ++q) {
+      const int64_t j = ci[q];
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        a = fma(li[c], X[j * P + c], a);
+        b = fma(Lam[j * P + c], xi[c], b);
+      }
+      g[q] = -0.5 * (a + b);
+    }
+  }
+}
+
 // dst[i] = src[i] (FP64 block copy)
 __global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, size_t count) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -311,6 +341,16 @@ hipError_t launch_add_f32(double* x, const float* d, size_t count, hipStream_t s
 hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy, dim3(flat_grid(count)), dim3(WG), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern_grad(int p, const bmr_csr_t& A, const double* Lam, const double* X, double* g,
+                               hipStream_t s) {
+  const int grid = stream_grid(A.n);
+#define L5(P) \
+  hipLaunchKernelGGL(k_pattern_grad<P>, dim3(grid), dim3(WG), 0, s, A.row_ptr, A.col_idx, Lam, X, g, A.n)
+  BMR_DISPATCH_P(p, L5)
+#undef L5
   return hipGetLastError();
 }
 

@@ -678,6 +678,13 @@ int bmr_spmm_f32(const bmr_csr_t* A, const float* val32, const float* V, float* 
   return launch_spmm<float>(p, *A, val32, V, W, stream) == hipSuccess ? BMR_CONVERGED : BMR_HIP_ERROR;
 }
 
+int bmr_pattern_grad(const bmr_csr_t* A, const double* Lam, const double* X, int p, double* grad,
+                     hipStream_t stream) {
+  if (!csr_valid(A) || !Lam || !X || !grad || p < 1 || p > BMR_MAX_P) return BMR_INVALID_ARG;
+  if (A->nnz == 0) return BMR_CONVERGED;
+  return launch_pattern_grad(p, *A, Lam, X, grad, stream) == hipSuccess ? BMR_CONVERGED : BMR_HIP_ERROR;
+}
+
 int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* norms,
                  void* workspace, size_t workspace_bytes, hipStream_t stream) {
   if (!csr_valid(A) || !B || !X || !norms || !workspace || p < 1 || p > BMR_MAX_P) return BMR_INVALID_ARG;
