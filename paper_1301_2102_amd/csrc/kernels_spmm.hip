@@ -144,12 +144,32 @@ __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t*
     }
   } else {
     constexpr int U = LPR < 8 ? LPR : 8;
+    // with fewer than 8 lanes per row a stencil row spans two chunks: their
+    // index and value loads are issued together, one dependent round trip
+    // less per row (with 8 or more lanes the second load would be wasted)
+    constexpr bool PF = LPR < 8;
     const bool mine = c * CPL < P;
-    for (int base = s; base < e; base += LPR) {
+    int colA = 0, colB = 0;
+    T vA = T(0), vB = T(0);
+    if constexpr (PF) {
+      if (s + c < e) {
+        colA = ci[s + c];
+        vA = va[s + c];
+      }
+      if (s + LPR + c < e) {
+        colB = ci[s + LPR + c];
+        vB = va[s + LPR + c];
+      }
+    }
+    int chunk = 0;
+    for (int base = s; base < e; base += LPR, ++chunk) {
       const int idx = base + c;
       int col = 0;
       T v = T(0);
-      if (idx < e) {
+      if (PF && chunk < 2) {
+        col = chunk == 0 ? colA : colB;
+        v = chunk == 0 ? vA : vB;
+      } else if (idx < e) {
         col = ci[idx];
         v = va[idx];
       }
