@@ -107,16 +107,27 @@ __device__ inline void vstore(T* __restrict__ p, const T (&x)[CPL]) {
 // order (c0 = c * CPL).  In the group layout all lanes of a group call this
 // with the same row; lanes whose columns lie beyond p return zeros.
 template <int P, int LPR, int CPL, typename T>
+__device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
+                                 int s, int e, int c, T (&acc)[CPL]);
+
+template <int P, int LPR, int CPL, typename T>
 __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                   const T* __restrict__ va, const T* __restrict__ V, int64_t row, bool valid, int c,
                                   T (&acc)[CPL]) {
-#pragma unroll
-  for (int k = 0; k < CPL; ++k) acc[k] = T(0);
   int s = 0, e = 0;
   if (valid) {
     s = rp[row];
     e = rp[row + 1];
   }
+  gather_se<P, LPR, CPL>(ci, va, V, s, e, c, acc);
+}
+
+// the entries [s, e) of one row (s = e for an invalid row)
+template <int P, int LPR, int CPL, typename T>
+__device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
+                                 int s, int e, int c, T (&acc)[CPL]) {
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) acc[k] = T(0);
   if constexpr (LPR == 1) {
     constexpr int U = 8;
     for (int q = s; q < e; q += U) {
@@ -274,13 +285,32 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
 
   int64_t r0, r1;
   row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
+  // row pointers of the current step, loaded one step ahead
+  int s_nx = 0, e_nx = 0;
+  {
+    const int64_t row = r0 + wave * RPW + grp;
+    if (row < r1) {
+      s_nx = rp[row];
+      e_nx = rp[row + 1];
+    }
+  }
 
   for (int64_t base = r0; base < r1; base += RPG) {
     asm volatile("" ::: "memory");
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
+    const int s_cur = s_nx, e_cur = e_nx;
+    {
+      const int64_t rn = row + RPG;
+      s_nx = 0;
+      e_nx = 0;
+      if (rn < r1) {
+        s_nx = rp[rn];
+        e_nx = rp[rn + 1];
+      }
+    }
     T a[CPL];
-    gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
+    gather_se<P, LPR, CPL>(ci, va, V, s_cur, e_cur, c, a);
     T v[CPL], w[CPL];
     if constexpr (LN::ROW) {
       // the lane owns the whole row: everything stays in registers
