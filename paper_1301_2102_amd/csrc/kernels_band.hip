@@ -22,8 +22,9 @@
 // Work split inside the wavefront: lane l owns column l of the block (its
 // 4p band entries, kept in LDS) and column l of the S-hat window.  The
 // rotations of the two previous blocks are applied by all lanes at once; the
-// rotations of the block itself are generated column after column by the
-// owning lane and applied by the lanes to its right.  Floating-point
+// p rotations of each column of the block are generated together (lane t
+// makes rotation t from a prefix sum of squares) and applied by the lanes
+// owning the columns to its right.  Floating-point
 // contraction is off so that every scalar step rounds like the plain
 // one-vector-per-iteration formulation.
 #include <math.h>
@@ -50,20 +51,6 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
     __syncthreads();
   }
   if (threadIdx.x == 0) red[e] = sh[0];
-}
-
-// Givens pair zeroing b against a: r = hypot(a, b), c = a / r, s = b / r;
-// the identity (r = a) when b is exactly zero.  Returns r.
-__device__ inline double givens(double a, double b, double& c, double& s) {
-  if (b == 0.0) {
-    c = 1.0;
-    s = 0.0;
-    return a;
-  }
-  const double r = hypot(a, b);
-  c = a / r;
-  s = b / r;
-  return r;
 }
 
 __device__ inline void rotate(double c, double s, double& x, double& y) {
@@ -269,23 +256,50 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
     }
     const int64_t j = j0 + i + 1;
     const int piv = 2 * P + i;
-    if (tid == i) {  // new rotations zero the p subdiagonal entries of column j
-      double x = sh.col[i][piv], y[P];
+    {
+      // New rotations zero the p subdiagonal entries y_1..y_p of column j
+      // against its diagonal x_0.  Rotation t leaves
+      //     x_t = sqrt(x_0^2 + y_1^2 + ... + y_t^2)
+      // on the diagonal (x_0 itself while y_1..y_t are all zero, the identity
+      // rotations of givens()), and is c_t = x_{t-1} / x_t, s_t = y_t / x_t.
+      // Lane t-1 forms x_t from a prefix sum of squares over the lanes,
+      // scaled by a power of two near the column's largest magnitude, so the
+      // p rotations come out at once instead of through p dependent hypot
+      // calls.
+      const double x0 = sh.col[i][piv];
+      const double y = (tid < P) ? sh.col[i][piv + 1 + tid] : 0.0;
+      double m = fabs(y);
 #pragma unroll
-      for (int t = 0; t < P; ++t) y[t] = sh.col[i][piv + 1 + t];
+      for (int o = 1; o < 64; o <<= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      m = fmax(m, fabs(x0));
+      // power-of-two scale: exact, and keeps the squares in range
+      int ex = 0;
+      if (m > 0.0 && isfinite(m)) (void)frexp(m, &ex);
+      const double inv = ldexp(1.0, -ex), scl = ldexp(1.0, ex);
+      double ps = (y * inv) * (y * inv);
+      int nz = (y != 0.0) ? 1 : 0;
 #pragma unroll
-      for (int t = 0; t < P; ++t) {
-        double c, s;
-        const double r = givens(x, y[t], c, s);
-        sh.nrot[i][t][0] = c;
-        sh.nrot[i][t][1] = s;
-        if (s != 0.0) {
-          x = r;
-          y[t] = 0.0;
+      for (int o = 1; o < P; o <<= 1) {
+        const double a = __shfl_up(ps, o, 64);
+        const int b = __shfl_up(nz, o, 64);
+        if (tid >= o) {
+          ps += a;
+          nz |= b;
         }
       }
-      sh.col[i][piv] = x;
-      sh.piv = x;
+      const double xs = x0 * inv;
+      const double xt = nz ? scl * sqrt(xs * xs + ps) : x0;
+      double xprev = __shfl_up(xt, 1, 64);
+      if (tid == 0) xprev = x0;
+      if (tid < P) {
+        const bool ident = (y == 0.0);
+        sh.nrot[i][tid][0] = ident ? 1.0 : xprev / xt;
+        sh.nrot[i][tid][1] = ident ? 0.0 : y / xt;
+      }
+      if (tid == P - 1) {
+        sh.col[i][piv] = xt;
+        sh.piv = xt;
+      }
     }
     __syncthreads();
     if (!(sh.piv != 0.0)) {
