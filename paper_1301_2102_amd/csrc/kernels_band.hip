@@ -72,6 +72,7 @@ struct BandShared {
   double G[P * P], Q[P * P], Pm[P * P];
   double T1[P][P], T2[P][P], Gam[P][P];
   double araw[P], beta[P];
+  double Wg[P * MAXB], Vg[P * MAXB];  // W^T g_b and V_k^T g_b (bench inner products)
   double rot[2][P][P][2];  // rotations of blocks k-2 and k-1
   double nrot[P][P][2];    // rotations of block k
   double col[P][4 * P + 1];  // column l of H-bar, rows of blocks k-2 .. k+1
@@ -91,6 +92,10 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
     sh.G[e] = red[off_G(P) + e];
     sh.Q[e] = red[off_Q(P) + e];
     sh.Pm[e] = red[off_P(P) + e];
+  }
+  for (int e = tid; e < P * nb; e += 64) {
+    sh.Wg[e] = red[off_Wg(P) + e];
+    sh.Vg[e] = red[off_Vg(P, nb) + e];
   }
   if (tid < P) sh.araw[tid] = sqrt(red[off_a(P) + tid]);
   __syncthreads();
@@ -152,8 +157,8 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
   __syncthreads();
   if (tid >= taken && tid < nb) {
     const int b = tid;
-    const double* Wg = red + off_Wg(P);
-    const double* Vg = red + off_Vg(P, nb);
+    const double* Wg = sh.Wg;
+    const double* Vg = sh.Vg;
     double cf[P];
 #pragma unroll
     for (int l = 0; l < P; ++l) {
