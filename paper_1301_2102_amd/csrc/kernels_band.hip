@@ -24,14 +24,10 @@
 // rotations of the two previous blocks are applied by all lanes at once; the
 // p rotations of each column of the block are generated together (lane t
 // makes rotation t from a prefix sum of squares) and applied by the lanes
-// owning the columns to its right.  Floating-point
-// contraction is off so that every scalar step rounds like the plain
-// one-vector-per-iteration formulation.
+// owning the columns to its right.
 #include <math.h>
 
 #include "bmr_internal.hpp"
-
-#pragma clang fp contract(off)
 
 namespace bmr {
 namespace {
@@ -51,6 +47,17 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
     __syncthreads();
   }
   if (threadIdx.x == 0) red[e] = sh[0];
+}
+
+// The band kernel runs as a single wavefront (64 lanes).  Its barriers only
+// have to order LDS accesses between the lanes of that wavefront, which the
+// LDS executes in issue order; __syncthreads() would add a workgroup-scope
+// fence, which waits for every outstanding global store (the R rows, Z, the
+// residuals and the history written as the loop goes) on each call.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ inline void rotate(double c, double s, double& x, double& y) {
@@ -98,12 +105,12 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
     sh.Vg[e] = red[off_Vg(P, nb) + e];
   }
   if (tid < P) sh.araw[tid] = sqrt(red[off_a(P) + tid]);
-  __syncthreads();
+  wave_sync();
   for (int e = tid; e < P * P; e += 64) {
     const int r = e / P, c = e % P;
     sh.Ak[r][c] = (r >= c) ? sh.G[r * P + c] : sh.G[c * P + r];
   }
-  __syncthreads();
+  wave_sync();
   for (int e = tid; e < P * P; e += 64) {
     const int l = e / P, m = e % P;
     double t = 0.0, u = 0.0;
@@ -114,7 +121,7 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
     sh.T1[l][m] = t;  // (A_k^T G)(l, m)
     sh.T2[l][m] = u;  // (Pm A_k)(l, m)
   }
-  __syncthreads();
+  wave_sync();
   // Gram of W - V_k A_k:  Q - A_k^T G - G^T A_k + A_k^T Pm A_k
   for (int e = tid; e < P * P; e += 64) {
     const int l = e / P, m = e % P;
@@ -122,14 +129,14 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
     for (int r = 0; r < P; ++r) t += sh.Ak[r][l] * sh.T2[r][m];
     sh.Gam[l][m] = sh.Q[l * P + m] - sh.T1[l][m] - sh.T1[m][l] + t;
   }
-  __syncthreads();
+  wave_sync();
   // symmetric working copy in T2 (off-diagonal entries averaged)
   for (int e = tid; e < P * P; e += 64) {
     const int l = e / P, m = e % P;
     sh.T2[l][m] = (l == m) ? sh.Gam[l][l] : 0.5 * (sh.Gam[l][m] + sh.Gam[m][l]);
     sh.Bk[l][m] = 0.0;
   }
-  __syncthreads();
+  wave_sync();
   // right-looking Cholesky T2 = B_k^T B_k; each entry sees its subtractions
   // in the same order as the row-oriented recurrence
 #pragma unroll 1
@@ -141,34 +148,39 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
       sh.flag = ok;
       sh.piv = ok ? sqrt(d) : 0.0;
     }
-    __syncthreads();
+    wave_sync();
     if (!sh.flag) return false;
     if (tid == l) sh.Bk[l][l] = sh.piv;
     if (tid > l && tid < P) sh.Bk[l][tid] = sh.T2[l][tid] / sh.piv;
-    __syncthreads();
+    wave_sync();
     for (int e = tid; e < P * P; e += 64) {
       const int r = e / P, c = e % P;
       if (r > l && c > l) sh.T2[r][c] -= sh.Bk[l][r] * sh.Bk[l][c];
     }
-    __syncthreads();
+    wave_sync();
   }
-  // bench: V_{k+1}^T g_b = B_k^{-T} (W^T g_b - A_k^T V_k^T g_b), one lane per vector
-  for (int e = tid; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
-  __syncthreads();
-  if (tid >= taken && tid < nb) {
+  // bench: V_{k+1}^T g_b = B_k^{-T} (W^T g_b - A_k^T V_k^T g_b), one lane per
+  // vector; lane b writes row b of the coefficients (zeros for used vectors)
+  if (tid < MAXB) {
     const int b = tid;
+    const bool live = b >= taken && b < nb;
     const double* Wg = sh.Wg;
     const double* Vg = sh.Vg;
     double cf[P];
 #pragma unroll
     for (int l = 0; l < P; ++l) {
-      double gw = Wg[l * nb + b];
-      for (int r = 0; r < P; ++r) gw -= sh.Ak[r][l] * Vg[r * nb + b];
+      double c = 0.0;
+      if (live) {
+        double gw = Wg[l * nb + b];
+        for (int r = 0; r < P; ++r) gw -= sh.Ak[r][l] * Vg[r * nb + b];
 #pragma unroll
-      for (int r = 0; r < l; ++r) gw -= sh.Bk[r][l] * cf[r];
-      cf[l] = gw / sh.Bk[l][l];
-      st->bcoef[b * MAXP + l] = cf[l];
+        for (int r = 0; r < l; ++r) gw -= sh.Bk[r][l] * cf[r];
+        c = gw / sh.Bk[l][l];
+      }
+      cf[l] = c;
+      st->bcoef[b * MAXP + l] = c;
     }
+    for (int l = P; l < MAXP; ++l) st->bcoef[b * MAXP + l] = 0.0;
   }
   for (int e = tid; e < P * P; e += 64) {
     const int r = e / P, c = e % P;
@@ -178,7 +190,7 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
     st->P2B[r * MAXP + c] = sh.Bk[r][c];
   }
   if (tid < P) st->araw[tid] = sh.araw[tid];
-  __syncthreads();
+  wave_sync();
   return true;
 }
 
@@ -229,7 +241,7 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
     if (r >= 3 * P) v = (r - 3 * P <= l) ? sh.Bk[r - 3 * P][l] : 0.0;
     sh.col[l][r] = v;
   }
-  __syncthreads();
+  wave_sync();
   // rotations of columns j-2p .. j-1 that lie in blocks k-2 (i >= l) and k-1
   if (tid < P) {
     const int l = tid;
@@ -248,8 +260,10 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
         for (int t = 0; t < P; ++t) sh.col[l][base + 1 + t] = y[t];
       }
   }
-  __syncthreads();
+  wave_sync();
 
+  // 1 / ||b_q|| of this lane's column (0 for a zero right-hand side)
+  const double binv = (tid < P && sh.beta[tid] > 0.0) ? 1.0 / sh.beta[tid] : 0.0;
   int lstar = P, finished = 0, status = STATUS_RUNNING;
 #pragma unroll 1
   for (int i = 0; i < P; ++i) {
@@ -275,7 +289,7 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
       const double y = (tid < P) ? sh.col[i][piv + 1 + tid] : 0.0;
       double m = fabs(y);
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      for (int o = 1; o < 16; o <<= 1) m = fmax(m, __shfl_xor(m, o, 16));
       m = fmax(m, fabs(x0));
       // power-of-two scale: exact, and keeps the squares in range
       int ex = 0;
@@ -298,15 +312,16 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
       if (tid == 0) xprev = x0;
       if (tid < P) {
         const bool ident = (y == 0.0);
-        sh.nrot[i][tid][0] = ident ? 1.0 : xprev / xt;
-        sh.nrot[i][tid][1] = ident ? 0.0 : y / xt;
+        const double rinv = 1.0 / xt;
+        sh.nrot[i][tid][0] = ident ? 1.0 : xprev * rinv;
+        sh.nrot[i][tid][1] = ident ? 0.0 : y * rinv;
       }
       if (tid == P - 1) {
         sh.col[i][piv] = xt;
         sh.piv = xt;
       }
     }
-    __syncthreads();
+    wave_sync();
     if (!(sh.piv != 0.0)) {
       if (tid == 0) {
         halt_with(st, isfinite(sh.piv) ? BMR_SINGULAR_R : BMR_NONFINITE, REASON_ERROR);
@@ -346,20 +361,18 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
         sh.s2[q][i + 1 + t] = y[t];
         ss += y[t] * y[t];
       }
-      ratio = sh.beta[q] > 0.0 ? sqrt(ss) / sh.beta[q] : 0.0;
+      ratio = binv > 0.0 ? sqrt(ss) * binv : 0.0;
       st->Z[i * MAXP + q] = x;
       st->rho[q] = ratio;
       if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
     }
-    // stopping test over the wavefront: max ratio, any non-finite value
-    double worst = ratio;
-    int bad = isfinite(ratio) ? 0 : 1;
+    // stopping test over the columns (lanes 0..p-1 of the first 16): the
+    // largest ratio, with a non-finite ratio counted as +inf
+    double worst = isfinite(ratio) ? ratio : INFINITY;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      worst = fmax(worst, __shfl_xor(worst, o, 64));
-      bad |= __shfl_xor(bad, o, 64);
-    }
-    const int f = bad ? 2 : (worst < tol) ? 1 : (j >= max_iter) ? 3 : 0;
+    for (int o = 1; o < 16; o <<= 1) worst = fmax(worst, __shfl_xor(worst, o, 16));
+    worst = __shfl(worst, 0, 64);  // every lane takes lane 0's decision
+    const int f = (worst == INFINITY) ? 2 : (worst < tol) ? 1 : (j >= max_iter) ? 3 : 0;
     if (f == 2) {
       if (tid == 0) {
         halt_with(st, BMR_NONFINITE, REASON_ERROR);
@@ -373,7 +386,7 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
       lstar = i + 1;
       break;
     }
-    __syncthreads();
+    wave_sync();
   }
   if (finished && lstar == 0) {
     if (tid == 0) halt_with(st, status, REASON_FINISHED);
@@ -415,12 +428,12 @@ __global__ __launch_bounds__(64) void k_band(int mode, const double* __restrict_
   __shared__ BandShared<P> sh;
   const int tid = threadIdx.x;
   if (tid == 0) sh.flag = st->halt;
-  __syncthreads();
+  wave_sync();
   if (sh.flag) {
     if (tid == 0) st->k2 = 0;
     return;
   }
-  __syncthreads();
+  wave_sync();
   load_band_inputs<P>(st, sh);
   if (mode == 0) {
     if (!phase_a<P>(red, st, sh)) {
@@ -442,7 +455,7 @@ __global__ __launch_bounds__(64) void k_band(int mode, const double* __restrict_
       st->P2B[r * MAXP + c] = (r == c) ? 1.0 : 0.0;
     }
     for (int e = tid; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
-    __syncthreads();
+    wave_sync();
   }
   phase_b<P>(st, hist, sh);
 }
