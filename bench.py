@@ -36,7 +36,9 @@ def kernel_bytes(A, p, nb, esz=8):
     n, nnz = A.n, A.nnz
     blk = esz * n * p
     pass1 = (4 + esz) * nnz + 4 * (n + 1) + 3 * blk + esz * n * nb   # A, V_k, V_{k-1}, W out, bench in
-    pass2 = 8 * blk + 2 * esz * n * nb                               # W, V_k, V_{k+1}, M x3, X in/out, bench
+    # W, V_k, V_{k+1}, M_{k-2}, M_{k-1}, M_k every block iteration, X read and
+    # written once per three block iterations, the bench in and out
+    pass2 = 6 * blk + (2 * blk) // 3 + 2 * esz * n * nb
     spmm = (4 + esz) * nnz + 4 * (n + 1) + 2 * blk                   # A, V in, W out
     return {"pass1_spmm_gram": pass1, "pass2_update": pass2, "spmm": spmm}
 

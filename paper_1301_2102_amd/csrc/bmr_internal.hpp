@@ -73,7 +73,7 @@ struct DevState {
   double Ra[MAXP * MAXP];     // R rows of block k-2 (lower part), columns of block k
   double Rb[MAXP * MAXP];     // R rows of block k-1
   double Rc[MAXP * MAXP];     // R rows of block k (upper triangular)
-  double Z[MAXP * MAXP];      // row l = z_j^T for j = (k-1)p + l + 1
+  double Z[3][MAXP * MAXP];   // block b, ring b mod 3: row l = z_j^T for j = (b-1)p + l + 1
   double bcoef[MAXB * MAXP];  // bench update: g_b -= V_{k+1} bcoef[b]
   double araw[MAXP];          // ||A u_j|| of the block's columns
   double rho[MAXP];           // last rho_j / beta

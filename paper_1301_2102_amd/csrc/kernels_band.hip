@@ -362,7 +362,7 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
         ss += y[t] * y[t];
       }
       ratio = binv > 0.0 ? sqrt(ss) * binv : 0.0;
-      st->Z[i * MAXP + q] = x;
+      st->Z[k % 3][i * MAXP + q] = x;
       st->rho[q] = ratio;
       if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
     }
@@ -388,10 +388,8 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
     }
     wave_sync();
   }
-  if (finished && lstar == 0) {
-    if (tid == 0) halt_with(st, status, REASON_FINISHED);
-    return;
-  }
+  // A finished block (lstar = 0 included) still goes through pass 2, which
+  // applies the X updates the earlier blocks of its group left pending.
   if (finished) {
     if (tid == 0) {
       st->lstar = lstar;

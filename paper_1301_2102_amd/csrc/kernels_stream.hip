@@ -8,6 +8,12 @@
 // search directions of the block (eq. (4.1)),
 //     M_k = (V_k - M_{k-2} R_a - M_{k-1} R_b) R_c^{-1},
 // and adds them to the iterate (eq. (4.2)), X += M_k(:, 1:l*) Z_k(1:l*, :).
+// The iterate is updated once per group of three blocks (k = 3, 6, 9, ...,
+// and at the block where the iteration stops): pass 2 of block k reads
+// M_{k-2} and M_{k-1} for the recurrence anyway, so it adds the pending
+// products M_{k-2} Z_{k-2} and M_{k-1} Z_{k-1} before M_k Z_k in the same
+// order as block-by-block updates would (the stored X is exact), and X is
+// read and written a third as often.
 // Every per-row operation runs in the order of the one-vector-per-iteration
 // algorithm, so that only the inner products differ in rounding.
 // The p x p coefficient blocks come from the band kernel through the device
@@ -27,7 +33,13 @@ __global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restri
                                               const DevState* __restrict__ st) {
   const int64_t k = st->k2;
   if (k == 0) return;
-  __shared__ T sA[P * P], sB[P * P], sRa[P * P], sRb[P * P], sRc[P * P], sZ[P * P], sBc[MAXB * P];
+  // X is updated at the last block of each group of three and at the block
+  // where the iteration stops; f0 is the first block of the group.
+  const bool finishing = st->reason == REASON_FINISHED;
+  const bool upd_x = finishing || (k % 3 == 0);
+  const int64_t f0 = k - (k - 1) % 3;
+  __shared__ T sA[P * P], sB[P * P], sRa[P * P], sRb[P * P], sRc[P * P], sBc[MAXB * P];
+  __shared__ T sZ[3][P * P];  // Z of blocks k-2, k-1, k
   for (int e = threadIdx.x; e < P * P; e += WG) {
     const int r = e / P, c = e % P, o = r * MAXP + c;
     sA[e] = (T)st->P2A[o];
@@ -35,7 +47,7 @@ __global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restri
     sRa[e] = (T)st->Ra[o];
     sRb[e] = (T)st->Rb[o];
     sRc[e] = (T)st->Rc[o];
-    sZ[e] = (T)st->Z[o];
+    for (int d = 0; d < 3; ++d) sZ[d][e] = (T)st->Z[(k + 1 + d) % 3][o];
   }
   for (int e = threadIdx.x; e < MAXB * P; e += WG) sBc[e] = (T)st->bcoef[(e / P) * MAXP + (e % P)];
   __syncthreads();
@@ -81,9 +93,8 @@ __global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restri
     }
     asm volatile("" ::: "memory");
     // search directions of the block
-    T mk[P];
+    T mk[P], m2[P], m1[P];
     {
-      T m2[P], m1[P];
 #pragma unroll
       for (int c = 0; c < P; ++c) {
         m2[c] = Mm2[row * P + c];
@@ -108,19 +119,34 @@ __global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restri
 #pragma unroll
     for (int c = 0; c < P; ++c) Mk[row * P + c] = mk[c];
     asm volatile("" ::: "memory");
-    // progressive update of the iterate
-    T x[P];
+    // progressive update of the iterate: the pending blocks of the group,
+    // oldest first (M_{k-2}, M_{k-1} are complete blocks, M_k has l* columns)
+    if (upd_x) {
+      T x[P];
 #pragma unroll
-    for (int c = 0; c < P; ++c) x[c] = X[row * P + c];
+      for (int c = 0; c < P; ++c) x[c] = X[row * P + c];
+      if (f0 <= k - 2) {
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
-      if (l < lstar) {
+        for (int l = 0; l < P; ++l)
 #pragma unroll
-        for (int c = 0; c < P; ++c) x[c] = fma(mk[l], sZ[l * P + c], x[c]);
+          for (int c = 0; c < P; ++c) x[c] = fma(m2[l], sZ[0][l * P + c], x[c]);
       }
-    }
+      if (f0 <= k - 1) {
 #pragma unroll
-    for (int c = 0; c < P; ++c) X[row * P + c] = x[c];
+        for (int l = 0; l < P; ++l)
+#pragma unroll
+          for (int c = 0; c < P; ++c) x[c] = fma(m1[l], sZ[1][l * P + c], x[c]);
+      }
+#pragma unroll
+      for (int l = 0; l < P; ++l) {
+        if (l < lstar) {
+#pragma unroll
+          for (int c = 0; c < P; ++c) x[c] = fma(mk[l], sZ[2][l * P + c], x[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < P; ++c) X[row * P + c] = x[c];
+    }
   }
 }
 
