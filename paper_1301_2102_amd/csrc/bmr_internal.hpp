@@ -24,15 +24,14 @@ enum : int {
 
 // Number of reduced entries pass 1 produces for block size p and bench nb:
 // G = V_k^T W (p x p), Q = W^T W (p x p), P = V_k^T V_k (p x p),
-// a = column norms^2 of A V_k (p), W^T g (p x nb), V_k^T g (p x nb), g^T g (nb x nb).
-__host__ __device__ constexpr int n_entries(int p, int nb) { return 3 * p * p + p + 2 * p * nb + nb * nb; }
+// a = column norms^2 of A V_k (p), W^T g (p x nb), V_k^T g (p x nb).
+__host__ __device__ constexpr int n_entries(int p, int nb) { return 3 * p * p + p + 2 * p * nb; }
 __host__ __device__ constexpr int off_G(int) { return 0; }
 __host__ __device__ constexpr int off_Q(int p) { return p * p; }
 __host__ __device__ constexpr int off_P(int p) { return 2 * p * p; }
 __host__ __device__ constexpr int off_a(int p) { return 3 * p * p; }
 __host__ __device__ constexpr int off_Wg(int p) { return 3 * p * p + p; }
 __host__ __device__ constexpr int off_Vg(int p, int nb) { return 3 * p * p + p + p * nb; }
-__host__ __device__ constexpr int off_gg(int p, int nb) { return 3 * p * p + p + 2 * p * nb; }
 
 // Device-resident state of one solve.  Written by the host once, then only by
 // the single-workgroup band kernel (and by the host while the device loop is

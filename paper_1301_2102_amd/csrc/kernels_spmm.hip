@@ -265,8 +265,7 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   for (int e = tid; e < P * P; e += WG) sBp[e / P][e % P] = (T)st->Bprev[(e / P) * MAXP + (e % P)];
   __syncthreads();
 
-  constexpr int NGG = (MAXB * MAXB + LPR - 1) / LPR;
-  T aA[CPL], aGg[NGG];
+  T aA[CPL];
   // one-lane-per-row (p <= 2) accumulators
   T lG[CPL][CPL], lQ[CPL][CPL], lP[CPL][CPL], lWg[CPL][MAXB], lVg[CPL][MAXB];
   // matrix-core accumulators: p <= 8: m0 = X^T X, m1 = X^T g with X = [V_k W];
@@ -280,8 +279,6 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) lWg[cc][b] = lVg[cc][b] = T(0);
   }
-#pragma unroll
-  for (int q = 0; q < NGG; ++q) aGg[q] = T(0);
 
   int64_t r0, r1;
   row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
@@ -347,11 +344,6 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
             lWg[cc][b] = fma(w[cc], g[b], lWg[cc][b]);
             lVg[cc][b] = fma(v[cc], g[b], lVg[cc][b]);
           }
-#pragma unroll
-        for (int q = 0; q < NGG; ++q) {
-          const int e = q;  // LPR = 1: entry (e / MAXB, e % MAXB)
-          aGg[q] = fma(g[e / MAXB], g[e % MAXB], aGg[q]);
-        }
       }
     } else {
       // this lane's columns of V_k and V_{k-1}; its bench entry
@@ -384,14 +376,6 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         aA[cc] = fma(a[cc], a[cc], aA[cc]);
       }
       if (valid && c0 < P) vstore<CPL>(W + row * P + c0, w);
-      // g^T g, spread over the lanes of the group
-      if (live_bench) {
-#pragma unroll
-        for (int q = 0; q < NGG; ++q) {
-          const int e = c + q * LPR;
-          if (e < MAXB * MAXB) aGg[q] = fma(sg[grp * MAXB + e / MAXB], sg[grp * MAXB + e % MAXB], aGg[q]);
-        }
-      }
       __builtin_amdgcn_wave_barrier();
       // Gram products on the matrix cores, four staged rows per product
       const int m = lane % 16, rq = lane / 16;
@@ -427,8 +411,6 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) aA[cc] = group_sum<LPR>(aA[cc]);
-#pragma unroll
-  for (int q = 0; q < NGG; ++q) aGg[q] = group_sum<LPR>(aGg[q]);
   if constexpr (LN::ROW) {
 #pragma unroll
     for (int r = 0; r < CPL; ++r)
@@ -492,11 +474,6 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
     for (int cc = 0; cc < CPL; ++cc) {
       const int col = c0 + cc;
       if (col < P) s[off_a(P) + col] = aA[cc];
-    }
-#pragma unroll
-    for (int q = 0; q < NGG; ++q) {
-      const int e = c + q * LPR, b = e / MAXB, b2 = e % MAXB;
-      if (e < MAXB * MAXB && b < nb && b2 < nb) s[off_gg(P, nb) + b * nb + b2] = aGg[q];
     }
   }
   __syncthreads();
