@@ -186,14 +186,14 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
 
 /* W = A V, the block operator application of Algorithm 7.1 (A applied to p
  * vectors at once; each row of A is read once for all p columns).
- * V, W: device, n x p row-interleaved, must not alias.  Asynchronous: returns
- * after enqueueing on stream. */
+ * V, W: device, n x p row-interleaved, 16-byte aligned, must not alias.
+ * Asynchronous: returns after enqueueing on stream. */
 int bmr_spmm(const bmr_csr_t* A, const double* V, double* W, int p, hipStream_t stream);
 
 /* W = A V in binary32 (the block operator of the mixed-precision inner
  * solve): the structure of A with the binary32 values val32 (device, nnz
- * entries), V and W device n x p binary32 row-interleaved, not aliasing.
- * Products and sums in binary32.  Asynchronous. */
+ * entries), V and W device n x p binary32 row-interleaved, 16-byte aligned,
+ * not aliasing.  Products and sums in binary32.  Asynchronous. */
 int bmr_spmm_f32(const bmr_csr_t* A, const float* val32, const float* V, float* W, int p, hipStream_t stream);
 
 /* Gradient of a scalar loss L(X) of the solution X = A^{-1} B with respect to
@@ -213,7 +213,7 @@ int bmr_pattern_grad(const bmr_csr_t* A, const double* Lam, const double* X, int
 
 /* Explicit residual R = B - A X and its column norms (the quantity the
  * stopping test of Algorithm 7.1 bounds).
- *   B, X       device, n x p row-interleaved.
+ *   B, X       device, n x p row-interleaved; X 16-byte aligned.
  *   R          device n x p output, or NULL to compute the norms only.
  *   norms      host, p doubles: ||b_i - A x_i||.
  *   workspace  device, >= bmr_workspace_bytes(n, 0, p, NULL) bytes.
