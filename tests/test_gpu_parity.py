@@ -219,3 +219,53 @@ def test_full_size_lap3d_128_p8_converged_properties():
     assert info.res_rec.max() < tol
     assert ex.max() < 10 * tol
     assert np.all(np.diff(info.hist, axis=0) <= 1e-14)
+
+
+@pytest.mark.parametrize("name", ["lap3d-128-p1", "lap3d-128-p16", "rand-1m-p16"])
+def test_full_size_prefix_other_workloads(name):
+    """The other full-size workloads (128^3 at p = 1 and p = 16, the random
+    sparse indefinite matrix with n = 2^20, p = 16): the first 32 band
+    iterations against the oracle element by element."""
+    A, B, _, _ = workload(name)
+    X, info, ro, _ = _both(A, B, 1e-30, 32)
+    assert info.band_iters == ro.iters == 32
+    _hist_close(info.hist, ro.hist)
+    assert _relcols(X, ro.X) <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["stress-64-k0", "stress-64-k4", "stress-64-k8", "stress-64-e3"])
+def test_full_size_stress_prefix(name):
+    """64^3 deflation-stress inputs at full size: the replacements of the
+    first 48 band iterations (the copy column at the initial QR; the
+    dependent candidate of iteration 1 for [e_1, A e_1, ...]) match the
+    oracle, and so do the iterate and the residual history."""
+    A, B, _, _ = workload(name)
+    X, info, ro, _ = _both(A, B, 1e-30, 48)
+    assert info.band_iters == ro.iters == 48
+    assert info.n_replaced == len(ro.replaced) >= 1
+    _hist_close(info.hist, ro.hist)
+    assert _relcols(X, ro.X) <= 1e-7
+
+
+@pytest.mark.parametrize("name", ["stress-64-k0", "stress-64-k4", "stress-64-k8", "stress-64-e3"])
+def test_full_size_stress_converged_properties(name):
+    """64^3 deflation-stress inputs solved to 1e-8 on the GPU: converged, the
+    explicit residual meets the tolerance, and the dependent column's
+    solution follows from the others (x_8 = x_1 for the copy column,
+    x_2 = e_1 for B = [e_1, A e_1, ...])."""
+    A, B, tol, mi = workload(name)
+    Ad = bmr.to_device(A, DEV)
+    Bd = _dev(B)
+    X, info = bmr.solve(Ad, Bd, tol=tol, max_iter=mi)
+    assert info.status == bmr.CONVERGED, info.status_name
+    assert info.n_replaced >= 1
+    beta = np.linalg.norm(B, axis=0)
+    ex = bmr.residual(Ad, Bd, X) / beta
+    assert ex.max() < 10 * tol
+    Xh = X.cpu().numpy()
+    if name.endswith("e3"):
+        e1 = np.zeros(A.n)
+        e1[0] = 1.0
+        assert np.linalg.norm(Xh[:, 1] - e1) <= 1e-8
+    else:
+        assert np.linalg.norm(Xh[:, 7] - Xh[:, 0]) <= 1e-8 * np.linalg.norm(Xh[:, 0])
