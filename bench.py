@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-6)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

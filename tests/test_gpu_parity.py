@@ -1,6 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
 
-Tolerances (derived in the design doc from the oracle's own rounding-order floor):
+Tolerances (derived from the oracle's own rounding-order floor: the oracle
+against itself on a row-permuted copy of the same system):
   * residual history rho_j / ||b_i||: |gpu - oracle| <= 1e-6 * oracle + 1e-13
     over the iterations before Lanczos loses global orthogonality;
   * X: max_i ||x_i^gpu - x_i^orc|| / ||x_i^orc|| <= 1e-8 at a fixed j in that
