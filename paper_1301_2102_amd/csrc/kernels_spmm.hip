@@ -145,10 +145,26 @@ __device__ inline void vstore_nt(T* __restrict__ p, const T (&x)[CPL]) {
 
 // acc[k] = sum over the entries of `row` of val * V[col*P + c0 + k], in CSR
 // order (c0 = c * CPL).  In the group layout all lanes of a group call this
-// with the same row; lanes whose columns lie beyond p return zeros.
-template <int P, int LPR, int CPL, typename T>
+// with the same row; lanes whose columns lie beyond p return zeros.  With OWN,
+// ov[0 .. CPL) also receives own[0 .. CPL) (zeros for own == nullptr), loaded
+// together with the gathered rows.
+template <int P, int LPR, int CPL, bool OWN = false, typename T>
 __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
-                                 int s, int e, int c, T (&acc)[CPL]);
+                                 int s, int e, int c, T (&acc)[CPL], const T* __restrict__ own = nullptr,
+                                 T* ov = nullptr);
+
+template <int CPL, typename T>
+__device__ inline void load_own(const T* __restrict__ own, T* ov) {
+  if (own) {
+    T x[CPL];
+    vload<CPL>(own, x);
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) ov[k] = x[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) ov[k] = T(0);
+  }
+}
 
 template <int P, int LPR, int CPL, typename T>
 __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -163,12 +179,13 @@ __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t*
 }
 
 // the entries [s, e) of one row (s = e for an invalid row)
-template <int P, int LPR, int CPL, typename T>
+template <int P, int LPR, int CPL, bool OWN, typename T>
 __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
-                                 int s, int e, int c, T (&acc)[CPL]) {
+                                 int s, int e, int c, T (&acc)[CPL], const T* __restrict__ own, T* ov) {
 #pragma unroll
   for (int k = 0; k < CPL; ++k) acc[k] = T(0);
   if constexpr (LPR == 1) {
+    if constexpr (OWN) load_own<CPL>(own, ov);
     constexpr int U = 8;
     for (int q = s; q < e; q += U) {
       int cq[U];
@@ -212,28 +229,54 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
         vB = ldnt(va + s + LPR + c);
       }
     }
-    int chunk = 0;
-    for (int base = s; base < e; base += LPR, ++chunk) {
+    int base = s;
+    if constexpr (PF) {
+      // the two prefetched chunks form one batch: every gathered load of the
+      // batch is issued before the first of them is consumed, so a row of up
+      // to 2 * LPR entries costs one round trip to memory for its V rows
+      if constexpr (OWN) load_own<CPL>(own, ov);
+      const int cnt = e - s;
+      T x[2 * LPR][CPL];
+#pragma unroll
+      for (int u = 0; u < 2 * LPR; ++u) {
+        const int cq = __shfl(u < LPR ? colA : colB, u % LPR, LPR);
+        if (u < cnt && mine) {
+          vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) x[u][k] = T(0);
+        }
+      }
+      // the values are passed round after the loads are in flight
+#pragma unroll
+      for (int u = 0; u < 2 * LPR; ++u) {
+        const T vq = __shfl(u < LPR ? vA : vB, u % LPR, LPR);
+        const T co = u < cnt ? vq : T(0);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) acc[k] = fma(co, x[u][k], acc[k]);
+      }
+      base = s + 2 * LPR;
+    } else if constexpr (OWN) {
+      load_own<CPL>(own, ov);
+    }
+    for (; base < e; base += LPR) {
       const int idx = base + c;
       int col = 0;
       T v = T(0);
-      if (PF && chunk < 2) {
-        col = chunk == 0 ? colA : colB;
-        v = chunk == 0 ? vA : vB;
-      } else if (idx < e) {
+      if (idx < e) {
         col = ldnt(ci + idx);
         v = ldnt(va + idx);
       }
+      // cnt > 0 here; the do-while lets the compiler see that every loaded
+      // entry is consumed before the next row starts
       const int cnt = min(LPR, e - base);
-      for (int q0 = 0; q0 < cnt; q0 += U) {
-        T co[U], x[U][CPL];
+      int q0 = 0;
+      do {
+        T x[U][CPL];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int cq = __shfl(col, q0 + u, LPR);
-          const T vq = __shfl(v, q0 + u, LPR);
-          const bool in = q0 + u < cnt;
-          co[u] = in ? vq : T(0);
-          if (in && mine) {
+          if (q0 + u < cnt && mine) {
             vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
           } else {
 #pragma unroll
@@ -241,10 +284,14 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
           }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+          const T vq = __shfl(v, q0 + u, LPR);
+          const T co = q0 + u < cnt ? vq : T(0);
 #pragma unroll
-          for (int k = 0; k < CPL; ++k) acc[k] = fma(co[u], x[u][k], acc[k]);
-      }
+          for (int k = 0; k < CPL; ++k) acc[k] = fma(co, x[u][k], acc[k]);
+        }
+        q0 += U;
+      } while (q0 < cnt);
     }
   }
 }
@@ -346,19 +393,40 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         e_nx = rp[rn + 1];
       }
     }
+    // For p <= 8 the row's V_{k-1} and bench entries are loaded before the
+    // gather, so that they travel together with the CSR entries, and its V_k
+    // row travels with the gathered rows.  For p > 8 the registers this
+    // takes would cost a wavefront per SIMD, and these loads follow the
+    // gather.
+    constexpr bool EARLY = true;
+    T v[CPL], w[CPL], vpo[CPL], vp[LN::ROW ? P : 1], g[LN::ROW ? MAXB : 1], gb = T(0);
+    auto load_prev = [&]() {
+      if constexpr (LN::ROW) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) vp[r] = valid ? Vp[row * P + r] : T(0);
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b)
+          g[b] = (live_bench && b >= taken && b < nb && valid) ? bench[row * nb + b] : T(0);
+      } else {
+        if (valid && c0 < P) {
+          vload_nt<CPL>(Vp + row * P + c0, vpo);
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) vpo[cc] = T(0);
+        }
+        if (c < MAXB && live_bench && c >= taken && c < nb && valid) gb = ldnt(bench + row * nb + c);
+      }
+    };
+    if constexpr (EARLY) load_prev();
     T a[CPL];
-    gather_se<P, LPR, CPL>(ci, va, V, s_cur, e_cur, c, a);
-    T v[CPL], w[CPL];
+    const T* own = (valid && c0 < P) ? V + row * P + c0 : nullptr;
+    gather_se<P, LPR, CPL, EARLY>(ci, va, V, s_cur, e_cur, c, a, own, v);
+    if constexpr (!EARLY) {
+      load_own<CPL>(own, v);
+      load_prev();
+    }
     if constexpr (LN::ROW) {
       // the lane owns the whole row: everything stays in registers
-      T vp[P], g[MAXB];
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        v[r] = valid ? V[row * P + r] : T(0);
-        vp[r] = valid ? Vp[row * P + r] : T(0);
-      }
-#pragma unroll
-      for (int b = 0; b < MAXB; ++b) g[b] = (live_bench && b >= taken && b < nb && valid) ? bench[row * nb + b] : T(0);
 #pragma unroll
       for (int col = 0; col < P; ++col) {
         T t = a[col];
@@ -386,22 +454,14 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
           }
       }
     } else {
-      // this lane's columns of V_k and V_{k-1}; its bench entry
-      T vpo[CPL];
-      if (valid && c0 < P) {
-        vload<CPL>(V + row * P + c0, v);
-        vload_nt<CPL>(Vp + row * P + c0, vpo);
-      } else {
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) v[cc] = vpo[cc] = T(0);
-      }
+      // stage this lane's columns of V_k and V_{k-1} and its bench entry
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc)
         if (c0 + cc < P) {
           sv[grp * SC + c0 + cc] = v[cc];
           svp[grp * P + c0 + cc] = vpo[cc];
         }
-      if (c < MAXB) sg[grp * MAXB + c] = (live_bench && c >= taken && c < nb && valid) ? ldnt(bench + row * nb + c) : T(0);
+      if (c < MAXB) sg[grp * MAXB + c] = gb;
       __builtin_amdgcn_wave_barrier();
       // known coefficients by symmetry: column l loses sum_{r >= l} B_{k-1}(l, r) V_{k-1}(:, r)
 #pragma unroll
