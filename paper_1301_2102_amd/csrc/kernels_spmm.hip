@@ -143,15 +143,51 @@ __device__ inline void vstore_nt(T* __restrict__ p, const T (&x)[CPL]) {
   }
 }
 
+// With fewer than 8 lanes per row (the group layout for p <= 8) a stencil
+// row spans two chunks of CSR entries.  Their index and value loads are
+// issued together ("lead" entries: s + c and s + LPR + c for lane c), and
+// the gathered V rows of both chunks are loaded before any is consumed.
+__host__ __device__ constexpr bool has_lead(int lpr) { return lpr > 1 && lpr < 8; }
+
+template <typename T>
+struct Lead {
+  int colA, colB;
+  T vA, vB;
+};
+
+template <int LPR, typename T>
+__device__ inline void load_lead(const int32_t* __restrict__ ci, const T* __restrict__ va, int s, int e, int c,
+                                 Lead<T>& q) {
+  q.colA = q.colB = 0;
+  q.vA = q.vB = T(0);
+  if (s + c < e) {
+    q.colA = ldnt(ci + s + c);
+    q.vA = ldnt(va + s + c);
+  }
+  if (s + LPR + c < e) {
+    q.colB = ldnt(ci + s + LPR + c);
+    q.vB = ldnt(va + s + LPR + c);
+  }
+}
+
 // acc[k] = sum over the entries of `row` of val * V[col*P + c0 + k], in CSR
 // order (c0 = c * CPL).  In the group layout all lanes of a group call this
 // with the same row; lanes whose columns lie beyond p return zeros.  With OWN,
 // ov[0 .. CPL) also receives own[0 .. CPL) (zeros for own == nullptr), loaded
-// together with the gathered rows.
-template <int P, int LPR, int CPL, bool OWN = false, typename T>
+// together with the gathered rows.  With PIPE (lead layouts only), *lead
+// holds this row's lead entries on entry and receives those of the entries
+// [s_nx, e_nx) of the next row on return, loaded while the gathered rows are
+// in flight.  mid() issues the caller's own loads: after the gathered loads
+// with PIPE, before the gather otherwise, so that they share a round trip.
+struct NoLoads {
+  __device__ void operator()() const {}
+};
+
+template <int P, int LPR, int CPL, bool OWN = false, bool PIPE = false, typename T, typename Mid = NoLoads>
 __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
                                  int s, int e, int c, T (&acc)[CPL], const T* __restrict__ own = nullptr,
-                                 T* ov = nullptr);
+                                 T* ov = nullptr, Lead<T>* lead = nullptr, int s_nx = 0, int e_nx = 0,
+                                 const Mid& mid = Mid());
 
 template <int CPL, typename T>
 __device__ inline void load_own(const T* __restrict__ own, T* ov) {
@@ -179,9 +215,12 @@ __device__ inline void gather_row(const int32_t* __restrict__ rp, const int32_t*
 }
 
 // the entries [s, e) of one row (s = e for an invalid row)
-template <int P, int LPR, int CPL, bool OWN, typename T>
+template <int P, int LPR, int CPL, bool OWN, bool PIPE, typename T, typename Mid>
 __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
-                                 int s, int e, int c, T (&acc)[CPL], const T* __restrict__ own, T* ov) {
+                                 int s, int e, int c, T (&acc)[CPL], const T* __restrict__ own, T* ov,
+                                 Lead<T>* lead, int s_nx, int e_nx, const Mid& mid) {
+  constexpr bool PF = has_lead(LPR);
+  if constexpr (!(PF && PIPE)) mid();
 #pragma unroll
   for (int k = 0; k < CPL; ++k) acc[k] = T(0);
   if constexpr (LPR == 1) {
@@ -212,26 +251,16 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
     }
   } else {
     constexpr int U = LPR < 8 ? LPR : 8;
-    // with fewer than 8 lanes per row a stencil row spans two chunks: their
-    // index and value loads are issued together, one dependent round trip
-    // less per row (with 8 or more lanes the second load would be wasted)
-    constexpr bool PF = LPR < 8;
     const bool mine = c * CPL < P;
-    int colA = 0, colB = 0;
-    T vA = T(0), vB = T(0);
-    if constexpr (PF) {
-      if (s + c < e) {
-        colA = ldnt(ci + s + c);
-        vA = ldnt(va + s + c);
-      }
-      if (s + LPR + c < e) {
-        colB = ldnt(ci + s + LPR + c);
-        vB = ldnt(va + s + LPR + c);
-      }
-    }
     int base = s;
     if constexpr (PF) {
-      // the two prefetched chunks form one batch: every gathered load of the
+      Lead<T> cur;
+      if constexpr (PIPE) {
+        cur = *lead;
+      } else {
+        load_lead<LPR>(ci, va, s, e, c, cur);
+      }
+      // the two lead chunks form one batch: every gathered load of the
       // batch is issued before the first of them is consumed, so a row of up
       // to 2 * LPR entries costs one round trip to memory for its V rows
       if constexpr (OWN) load_own<CPL>(own, ov);
@@ -239,7 +268,7 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
       T x[2 * LPR][CPL];
 #pragma unroll
       for (int u = 0; u < 2 * LPR; ++u) {
-        const int cq = __shfl(u < LPR ? colA : colB, u % LPR, LPR);
+        const int cq = __shfl(u < LPR ? cur.colA : cur.colB, u % LPR, LPR);
         if (u < cnt && mine) {
           vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
         } else {
@@ -247,10 +276,14 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
           for (int k = 0; k < CPL; ++k) x[u][k] = T(0);
         }
       }
+      if constexpr (PIPE) {
+        load_lead<LPR>(ci, va, s_nx, e_nx, c, *lead);
+        mid();
+      }
       // the values are passed round after the loads are in flight
 #pragma unroll
       for (int u = 0; u < 2 * LPR; ++u) {
-        const T vq = __shfl(u < LPR ? vA : vB, u % LPR, LPR);
+        const T vq = __shfl(u < LPR ? cur.vA : cur.vB, u % LPR, LPR);
         const T co = u < cnt ? vq : T(0);
 #pragma unroll
         for (int k = 0; k < CPL; ++k) acc[k] = fma(co, x[u][k], acc[k]);
@@ -305,6 +338,56 @@ __device__ inline void row_range(int64_t n, int n_wg, int L, int64_t& r0, int64_
   r0 = (int64_t)L * per * RPG;
   r1 = min(n, r0 + per * RPG);
 }
+
+// Row pointers and lead CSR entries of the row steps ahead of a lane's
+// current row, for a workgroup that walks its row range in steps of RPG.
+// Row pointers are loaded one step ahead; in the lead layouts the lead
+// entries of the next step are loaded during the gather of the current one
+// (gather_se with PIPE), which needs the row pointers two steps ahead.
+template <int LPR, int RPG, typename T>
+struct RowPipe {
+  static constexpr bool PIPE = has_lead(LPR);
+  int s_cur = 0, e_cur = 0, s_nx = 0, e_nx = 0, s_ahead = 0, e_ahead = 0;
+  Lead<T> lead;
+
+  __device__ void start(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const T* __restrict__ va,
+                        int64_t row, int64_t r1, int c) {
+    if (row < r1) {
+      s_cur = rp[row];
+      e_cur = rp[row + 1];
+    }
+    if constexpr (PIPE) {
+      if (row + RPG < r1) {
+        s_nx = rp[row + RPG];
+        e_nx = rp[row + RPG + 1];
+      }
+      load_lead<LPR>(ci, va, s_cur, e_cur, c, lead);
+      // wait once here, so that the loop does not wait for the lead loads
+      // (and with them for the previous step's stores) at every step
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+  }
+  // row pointers of the step after the ones already held (row: current row)
+  __device__ void load_ahead(const int32_t* __restrict__ rp, int64_t row, int64_t r1) {
+    const int64_t ra = row + (PIPE ? 2 : 1) * RPG;
+    s_ahead = e_ahead = 0;
+    if (ra < r1) {
+      s_ahead = rp[ra];
+      e_ahead = rp[ra + 1];
+    }
+  }
+  __device__ void advance() {
+    if constexpr (PIPE) {
+      s_cur = s_nx;
+      e_cur = e_nx;
+      s_nx = s_ahead;
+      e_nx = e_ahead;
+    } else {
+      s_cur = s_ahead;
+      e_cur = e_ahead;
+    }
+  }
+};
 
 // Sum x over the groups of a wavefront (lanes with equal c); the result is
 // valid in every lane.
@@ -369,38 +452,19 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
 
   int64_t r0, r1;
   row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
-  // row pointers of the current step, loaded one step ahead
-  int s_nx = 0, e_nx = 0;
-  {
-    const int64_t row = r0 + wave * RPW + grp;
-    if (row < r1) {
-      s_nx = rp[row];
-      e_nx = rp[row + 1];
-    }
-  }
+  RowPipe<LPR, RPG, T> pipe;
+  pipe.start(rp, ci, va, r0 + wave * RPW + grp, r1, c);
 
   for (int64_t base = r0; base < r1; base += RPG) {
     asm volatile("" ::: "memory");
     const int64_t row = base + wave * RPW + grp;
     const bool valid = row < r1;
-    const int s_cur = s_nx, e_cur = e_nx;
-    {
-      const int64_t rn = row + RPG;
-      s_nx = 0;
-      e_nx = 0;
-      if (rn < r1) {
-        s_nx = rp[rn];
-        e_nx = rp[rn + 1];
-      }
-    }
-    // For p <= 8 the row's V_{k-1} and bench entries are loaded before the
-    // gather, so that they travel together with the CSR entries, and its V_k
-    // row travels with the gathered rows.  For p > 8 the registers this
-    // takes would cost a wavefront per SIMD, and these loads follow the
-    // gather.
-    constexpr bool EARLY = true;
+    // The row pointers ahead, the row's V_{k-1} and bench entries travel
+    // together with the gathered rows (or the CSR entries without the
+    // pipeline); its own V_k row is loaded with the gathered rows.
     T v[CPL], w[CPL], vpo[CPL], vp[LN::ROW ? P : 1], g[LN::ROW ? MAXB : 1], gb = T(0);
-    auto load_prev = [&]() {
+    auto loads = [&]() {
+      pipe.load_ahead(rp, row, r1);
       if constexpr (LN::ROW) {
 #pragma unroll
         for (int r = 0; r < P; ++r) vp[r] = valid ? Vp[row * P + r] : T(0);
@@ -417,14 +481,11 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
         if (c < MAXB && live_bench && c >= taken && c < nb && valid) gb = ldnt(bench + row * nb + c);
       }
     };
-    if constexpr (EARLY) load_prev();
     T a[CPL];
     const T* own = (valid && c0 < P) ? V + row * P + c0 : nullptr;
-    gather_se<P, LPR, CPL, EARLY>(ci, va, V, s_cur, e_cur, c, a, own, v);
-    if constexpr (!EARLY) {
-      load_own<CPL>(own, v);
-      load_prev();
-    }
+    gather_se<P, LPR, CPL, true, RowPipe<LPR, RPG, T>::PIPE>(ci, va, V, pipe.s_cur, pipe.e_cur, c, a, own, v,
+                                                             &pipe.lead, pipe.s_nx, pipe.e_nx, loads);
+    pipe.advance();
     if constexpr (LN::ROW) {
       // the lane owns the whole row: everything stays in registers
 #pragma unroll
@@ -660,7 +721,9 @@ int pass1_grid(int64_t n, int p) {
 }
 
 static int spmm_grid(int64_t n, int p) {
-  return (int)std::max<int64_t>(1, (n + layout_rpg(p) - 1) / layout_rpg(p));  // one workgroup step each
+  // one workgroup step each: a grid that walks longer row ranges with the
+  // pass-1 pipeline measured slower for the plain product
+  return (int)std::max<int64_t>(1, (n + layout_rpg(p) - 1) / layout_rpg(p));
 }
 
 #define BMR_DISPATCH_P(p, MACRO) \

@@ -27,8 +27,13 @@ namespace {
 
 constexpr int WG = 256;
 
+// Wavefronts per SIMD that pass 2 asks the compiler to fit: one lane holds
+// several p-wide rows, and without a bound the compiler spends up to 256
+// registers on them at large p (one wavefront per SIMD).
+constexpr int pass2_waves(int p, int esz) { return p <= 8 ? 1 : (esz == 8 && p >= 12 ? 3 : 4); }
+
 template <int P, typename T>
-__global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(P, sizeof(T))))) void k_pass2(T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
                                               T* __restrict__ X, T* __restrict__ bench, int64_t n,
                                               const DevState* __restrict__ st) {
   const int64_t k = st->k2;
@@ -122,30 +127,36 @@ __global__ __launch_bounds__(WG) void k_pass2(T* __restrict__ Vbase, T* __restri
     // progressive update of the iterate: the pending blocks of the group,
     // oldest first (M_{k-2}, M_{k-1} are complete blocks, M_k has l* columns)
     if (upd_x) {
-      T x[P];
+      // for p > 8 a few columns at a time, so that the row of X does not
+      // sit in registers next to the three rows of M
+      constexpr int XC = P <= 8 ? P : (P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1));
 #pragma unroll
-      for (int c = 0; c < P; ++c) x[c] = X[row * P + c];
-      if (f0 <= k - 2) {
+      for (int c0 = 0; c0 < P; c0 += XC) {
+        T x[XC];
 #pragma unroll
-        for (int l = 0; l < P; ++l)
+        for (int c = 0; c < XC; ++c) x[c] = X[row * P + c0 + c];
+        if (f0 <= k - 2) {
 #pragma unroll
-          for (int c = 0; c < P; ++c) x[c] = fma(m2[l], sZ[0][l * P + c], x[c]);
-      }
-      if (f0 <= k - 1) {
+          for (int l = 0; l < P; ++l)
 #pragma unroll
-        for (int l = 0; l < P; ++l)
-#pragma unroll
-          for (int c = 0; c < P; ++c) x[c] = fma(m1[l], sZ[1][l * P + c], x[c]);
-      }
-#pragma unroll
-      for (int l = 0; l < P; ++l) {
-        if (l < lstar) {
-#pragma unroll
-          for (int c = 0; c < P; ++c) x[c] = fma(mk[l], sZ[2][l * P + c], x[c]);
+            for (int c = 0; c < XC; ++c) x[c] = fma(m2[l], sZ[0][l * P + c0 + c], x[c]);
         }
-      }
+        if (f0 <= k - 1) {
 #pragma unroll
-      for (int c = 0; c < P; ++c) X[row * P + c] = x[c];
+          for (int l = 0; l < P; ++l)
+#pragma unroll
+            for (int c = 0; c < XC; ++c) x[c] = fma(m1[l], sZ[1][l * P + c0 + c], x[c]);
+        }
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+          if (l < lstar) {
+#pragma unroll
+            for (int c = 0; c < XC; ++c) x[c] = fma(mk[l], sZ[2][l * P + c0 + c], x[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < XC; ++c) X[row * P + c0 + c] = x[c];
+      }
     }
   }
 }
