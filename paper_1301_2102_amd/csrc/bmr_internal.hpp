@@ -14,6 +14,18 @@ constexpr int MAXP = BMR_MAX_P;
 constexpr int MAXB = BMR_MAX_BENCH;
 constexpr int STATUS_RUNNING = 100;
 
+// The search directions and the iterate (eqs. (4.1)-(4.2)) are applied in
+// groups of s = group_len(p) blocks: pass 2 of the group's last block adds
+// the group's contributions to X from the group's Lanczos blocks and the two
+// search-direction blocks before the group.  s is capped so that the
+// 3 (s + 2) p x p coefficient blocks of a group fit in LDS.  V_k lives in
+// slot k mod ring_len(p) of the V ring.
+constexpr int MAXS = 12;
+__host__ __device__ constexpr int group_len(int p) {
+  return 1024 / (p * p) > MAXS ? MAXS : (1024 / (p * p) < 2 ? 2 : 1024 / (p * p));
+}
+__host__ __device__ constexpr int ring_len(int p) { return group_len(p) + 2; }
+
 // Why the device loop stopped (DevState::reason).
 enum : int {
   REASON_NONE = 0,
@@ -69,13 +81,26 @@ struct DevState {
   // ---- coefficients for pass 2 of block k2 ------------------------------
   double P2A[MAXP * MAXP];    // W' = W - V_k * P2A
   double P2B[MAXP * MAXP];    // V_{k+1} = W' * P2B^{-1} (upper triangular)
-  double Ra[MAXP * MAXP];     // R rows of block k-2 (lower part), columns of block k
-  double Rb[MAXP * MAXP];     // R rows of block k-1
-  double Rc[MAXP * MAXP];     // R rows of block k (upper triangular)
-  double Z[3][MAXP * MAXP];   // block b, ring b mod 3: row l = z_j^T for j = (b-1)p + l + 1
   double bcoef[MAXB * MAXP];  // bench update: g_b -= V_{k+1} bcoef[b]
   double araw[MAXP];          // ||A u_j|| of the block's columns
   double rho[MAXP];           // last rho_j / beta
+  // ---- search directions in groups of s = group_len(p) blocks -----------
+  // Block k = g + 1 + t of the group that starts after block g sits at
+  // position t.  Its search directions satisfy (eq. (4.1))
+  //     M_k = V_k C_k + M_{k-1} D_k + M_{k-2} E_k,
+  // C_k = R_c^{-1}, D_k = -R_b R_c^{-1}, E_k = -R_a R_c^{-1} (R_a, R_b, R_c: the
+  // rows of blocks k-2, k-1, k of R in the columns of block k), and it adds
+  // M_k Z_k to X (eq. (4.2); row l of Z_k is z_j^T for j = (k-1)p + l + 1).
+  // Columns l >= l* of a finishing block are zero in C, D, E and Z.
+  double gC[MAXS][MAXP * MAXP], gD[MAXS][MAXP * MAXP], gE[MAXS][MAXP * MAXP], gZ[MAXS][MAXP * MAXP];
+  // The flush after the group's last block g + m (m = flush_len) forms
+  //     out_o = [X if o = 0] + sum_{t<m} V_{g+1+t} Y[o][t] + M_g Y[o][MAXS] + M_{g-1} Y[o][MAXS+1],
+  // o = 0: X, o = 1: M_{g+m-1}, o = 2: M_{g+m} (the two blocks the next group
+  // starts from; not needed when the iteration stops at g + m).
+  double Y[3][MAXS + 2][MAXP * MAXP];
+  int64_t flush_block;  // g + m of the last group whose coefficients are in Y
+  int flush_len;        // m
+  int flush_keep;       // != 0: the flush also writes M_{g+m-1} and M_{g+m}
 };
 
 // Workspace carve-up (offsets into the caller's workspace).  The blocks V, M
@@ -106,8 +131,12 @@ hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, D
                          hipStream_t s);
 hipError_t launch_band(int p, int mode, const double* red, double* hist, DevState* st, hipStream_t s);
 template <typename T>
-hipError_t launch_pass2(int p, T* Vbase, T* Mbase, size_t slot_elems, T* X, T* bench, int64_t n, DevState* st,
-                        hipStream_t s);
+hipError_t launch_pass2(int p, T* Vbase, size_t slot_elems, T* bench, int64_t n, DevState* st, hipStream_t s);
+// The group's search directions into X (and the next group's two M blocks);
+// does nothing unless the band kernel recorded a group ending at block k.
+template <typename T>
+hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot_elems, T* X, int64_t n, int64_t k,
+                        const DevState* st, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s);
 template <typename T>

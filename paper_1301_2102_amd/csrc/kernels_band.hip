@@ -76,8 +76,16 @@ __device__ void halt_with(DevState* st, int status, int reason) {
 template <int P>
 struct BandShared {
   double Ak[P][P], Bk[P][P], Bp[P][P];
-  double G[P * P], Q[P * P], Pm[P * P];
-  double T1[P][P], T2[P][P], Gam[P][P];
+  union {
+    struct {  // phase A
+      double G[P * P], Q[P * P], Pm[P * P];
+      double T1[P][P], T2[P][P], Gam[P][P];
+    };
+    struct {  // phase B: R rows of blocks k-2, k-1, k in the block's columns, Z_k, C, D, E
+      double Ra[P][P], Rb[P][P], Rc[P][P], Zk[P][P], C[P][P], D[P][P], E[P][P];
+      double Tr[3][P][P];  // backward recurrence of the group coefficients (ring)
+    };
+  };
   double araw[P], beta[P];
   double Wg[P * MAXB], Vg[P * MAXB];  // W^T g_b and V_k^T g_b (bench inner products)
   double rot[2][P][P][2];  // rotations of blocks k-2 and k-1
@@ -220,6 +228,113 @@ __device__ void load_band_inputs(const DevState* __restrict__ st, BandShared<P>&
   if (tid < P) sh.beta[tid] = st->beta[tid];
 }
 
+// Search directions of block k in the grouped form (eq. (4.1)):
+//     M_k = V_k C_k + M_{k-1} D_k + M_{k-2} E_k,
+//     C_k = R_c^{-1},  D_k = -R_b C_k,  E_k = -R_a C_k,
+// on the leading l* columns (zero beyond), stored with Z_k (rows beyond l*
+// zero) at the block's position t in the group.  At the group's last block,
+// or when the iteration stops, the coefficients of the flush kernel follow
+// from the backward recurrence over the group's m blocks
+//     T_t = src_t + D_{t+1} T_{t+1} + E_{t+2} T_{t+2}   (t = m-1 .. 0),
+// T_t being the total weight with which M_{g+1+t} enters the output
+// (src_t = Z_t for X; the identity at t = m-2 or m-1, zero otherwise, for
+// the search-direction blocks M_{g+m-1} and M_{g+m} the next group starts
+// from):
+//     Y[o][t] = C_t T_t,  Y[o][M_g] = D_0 T_0 + E_1 T_1,  Y[o][M_{g-1}] = E_0 T_0.
+// Expanding the recurrence this way changes only the rounding of X.
+template <int P>
+__device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh, int64_t k, int lstar,
+                                    bool finishing) {
+  constexpr int S = group_len(P);
+  const int tid = threadIdx.x;
+  const int t = (int)((k - 1) % S);
+  // C = R_c^{-1} (upper triangular) on the leading l* columns: lane q forms row q
+  if (tid < P) {
+    const int q = tid;
+#pragma unroll 1
+    for (int i = 0; i < P; ++i) {
+      double c = 0.0;
+      if (i < lstar && q <= i) {
+        double a = (q == i) ? 1.0 : 0.0;
+        for (int r = q; r < i; ++r) a -= sh.C[q][r] * sh.Rc[r][i];
+        c = a / sh.Rc[i][i];
+      }
+      sh.C[q][i] = c;
+    }
+  }
+  wave_sync();
+  for (int e = tid; e < P * P; e += 64) {
+    const int q = e / P, i = e % P;
+    double d = 0.0, f = 0.0;
+    if (i < lstar) {
+      for (int r = 0; r <= i; ++r) {
+        d -= sh.Rb[q][r] * sh.C[r][i];
+        f -= sh.Ra[q][r] * sh.C[r][i];
+      }
+    }
+    const double z = (q < lstar) ? sh.Zk[q][i] : 0.0;
+    sh.D[q][i] = d;
+    sh.E[q][i] = f;
+    sh.Zk[q][i] = z;
+    st->gC[t][q * MAXP + i] = sh.C[q][i];
+    st->gD[t][q * MAXP + i] = d;
+    st->gE[t][q * MAXP + i] = f;
+    st->gZ[t][q * MAXP + i] = z;
+  }
+  wave_sync();
+  if (!finishing && t != S - 1) return;
+  // coefficients of positions u < t come from the earlier band kernels of
+  // the group, those of position t from LDS
+  auto cC = [&](int u, int r, int c) { return u == t ? sh.C[r][c] : st->gC[u][r * MAXP + c]; };
+  auto cD = [&](int u, int r, int c) { return u == t ? sh.D[r][c] : st->gD[u][r * MAXP + c]; };
+  auto cE = [&](int u, int r, int c) { return u == t ? sh.E[r][c] : st->gE[u][r * MAXP + c]; };
+  auto cZ = [&](int u, int r, int c) { return u == t ? sh.Zk[r][c] : st->gZ[u][r * MAXP + c]; };
+  const int m = t + 1;
+  const int nout = finishing ? 1 : 3;
+#pragma unroll 1
+  for (int o = 0; o < nout; ++o) {
+#pragma unroll 1
+    for (int u = m - 1; u >= 0; --u) {
+      const int s0 = u % 3, s1 = (u + 1) % 3, s2 = (u + 2) % 3;
+      for (int e = tid; e < P * P; e += 64) {
+        const int q = e / P, c = e % P;
+        double v = (o == 0) ? cZ(u, q, c) : ((u == m - 3 + o && q == c) ? 1.0 : 0.0);
+        if (u + 1 < m)
+          for (int i = 0; i < P; ++i) v += cD(u + 1, q, i) * sh.Tr[s1][i][c];
+        if (u + 2 < m)
+          for (int i = 0; i < P; ++i) v += cE(u + 2, q, i) * sh.Tr[s2][i][c];
+        sh.Tr[s0][q][c] = v;
+      }
+      wave_sync();
+      for (int e = tid; e < P * P; e += 64) {
+        const int q = e / P, c = e % P;
+        double y = 0.0;
+        for (int r = q; r < P; ++r) y += cC(u, q, r) * sh.Tr[s0][r][c];
+        st->Y[o][u][q * MAXP + c] = y;
+      }
+      wave_sync();
+    }
+    for (int e = tid; e < P * P; e += 64) {
+      const int q = e / P, c = e % P;
+      double yb = 0.0, ya = 0.0;
+      for (int i = 0; i < P; ++i) {
+        yb += cD(0, q, i) * sh.Tr[0][i][c];
+        ya += cE(0, q, i) * sh.Tr[0][i][c];
+      }
+      if (m >= 2)
+        for (int i = 0; i < P; ++i) yb += cE(1, q, i) * sh.Tr[1][i][c];
+      st->Y[o][MAXS][q * MAXP + c] = yb;
+      st->Y[o][MAXS + 1][q * MAXP + c] = ya;
+    }
+    wave_sync();
+  }
+  if (tid == 0) {
+    st->flush_len = m;
+    st->flush_keep = finishing ? 0 : 1;
+    st->flush_block = k;
+  }
+}
+
 // Phase B: Givens QR of the p new columns of H-bar, S-hat window, residuals,
 // stopping test, coefficients of the search directions and of the X update.
 // Columns live in LDS and the outer loops stay rolled: the kernel runs as a
@@ -333,9 +448,9 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
     if (tid < P) {
       const int q = tid;
       // column j of R: rows of blocks k-2, k-1 and k (lane q writes row q of each)
-      st->Ra[q * MAXP + i] = (q >= i) ? sh.col[i][q] : 0.0;
-      st->Rb[q * MAXP + i] = sh.col[i][P + q];
-      st->Rc[q * MAXP + i] = (q <= i) ? sh.col[i][2 * P + q] : 0.0;
+      sh.Ra[q][i] = (q >= i) ? sh.col[i][q] : 0.0;
+      sh.Rb[q][i] = sh.col[i][P + q];
+      sh.Rc[q][i] = (q <= i) ? sh.col[i][2 * P + q] : 0.0;
       if (q > i) {  // later columns of the block receive the rotations of column i
         double x = sh.col[q][piv], y[P];
 #pragma unroll
@@ -362,7 +477,7 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
         ss += y[t] * y[t];
       }
       ratio = binv > 0.0 ? sqrt(ss) * binv : 0.0;
-      st->Z[k % 3][i * MAXP + q] = x;
+      sh.Zk[i][q] = x;
       st->rho[q] = ratio;
       if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
     }
@@ -388,6 +503,8 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
     }
     wave_sync();
   }
+  wave_sync();
+  search_coefficients<P>(st, sh, k, lstar, finished);
   // A finished block (lstar = 0 included) still goes through pass 2, which
   // applies the X updates the earlier blocks of its group left pending.
   if (finished) {

@@ -409,9 +409,10 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   using acc4 = typename Ops::acc4;
   constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int64_t k = st->k;
-  const T* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
-  const T* __restrict__ Vp = Vbase + (size_t)((k + 2) % 3) * slot;  // V_{k-1}
-  T* __restrict__ W = Vbase + (size_t)((k + 1) % 3) * slot;         // becomes V_{k+1}
+  constexpr int R = ring_len(P);
+  const T* __restrict__ V = Vbase + (size_t)(k % R) * slot;
+  const T* __restrict__ Vp = Vbase + (size_t)((k + R - 1) % R) * slot;  // V_{k-1}
+  T* __restrict__ W = Vbase + (size_t)((k + 1) % R) * slot;             // becomes V_{k+1}
   const int nb = st->nb, taken = st->taken;
   const bool live_bench = taken < nb;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -4,18 +4,16 @@
 // Pass 2 touches every row once and keeps each row's p values in registers
 // (one lane per row): it finishes the orthogonalisation of the candidates,
 //     W' = W - V_k A_k,  V_{k+1} = W' B_k^{-1}          (forward substitution),
-// updates the substitute bench against V_{k+1} (Section 5.1), forms the
-// search directions of the block (eq. (4.1)),
-//     M_k = (V_k - M_{k-2} R_a - M_{k-1} R_b) R_c^{-1},
-// and adds them to the iterate (eq. (4.2)), X += M_k(:, 1:l*) Z_k(1:l*, :).
-// The iterate is updated once per group of three blocks (k = 3, 6, 9, ...,
-// and at the block where the iteration stops): pass 2 of block k reads
-// M_{k-2} and M_{k-1} for the recurrence anyway, so it adds the pending
-// products M_{k-2} Z_{k-2} and M_{k-1} Z_{k-1} before M_k Z_k in the same
-// order as block-by-block updates would (the stored X is exact), and X is
-// read and written a third as often.
-// Every per-row operation runs in the order of the one-vector-per-iteration
-// algorithm, so that only the inner products differ in rounding.
+// and updates the substitute bench against V_{k+1} (Section 5.1).  The
+// search directions of eq. (4.1) and the iterate update of eq. (4.2) are
+// applied once per group of s blocks (and at the block where the iteration
+// stops): with M_k = V_k C_k + M_{k-1} D_k + M_{k-2} E_k, the group's
+// contribution sum_k M_k Z_k to X, and the two search-direction blocks the
+// next group starts from, are combinations of the group's Lanczos blocks
+// V_{g+1} .. V_{g+s} and of M_g, M_{g-1}, with p x p coefficients that the
+// band kernel forms by a backward recurrence.  Per block iteration this
+// reads and writes three n x p blocks (W, V_k in, V_{k+1} out) instead of
+// six, plus (s + 5) blocks once per group.
 // The p x p coefficient blocks come from the band kernel through the device
 // state and are staged in LDS once per workgroup, rounded to the storage type
 // T (double, or float in the inner solve of the mixed-precision solver, whose
@@ -30,43 +28,30 @@ constexpr int WG = 256;
 // Wavefronts per SIMD that pass 2 asks the compiler to fit: one lane holds
 // several p-wide rows, and without a bound the compiler spends up to 256
 // registers on them at large p (one wavefront per SIMD).
-constexpr int pass2_waves(int p, int esz) { return p <= 8 ? 1 : (esz == 8 && p >= 12 ? 3 : 4); }
+constexpr int pass2_waves(int p, int esz) { return esz == 8 && p >= 12 ? 3 : 4; }
 
 template <int P, typename T>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(P, sizeof(T))))) void k_pass2(T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
-                                              T* __restrict__ X, T* __restrict__ bench, int64_t n,
-                                              const DevState* __restrict__ st) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(P, sizeof(T))))) void k_pass2(
+    T* __restrict__ Vbase, size_t slot, T* __restrict__ bench, int64_t n, const DevState* __restrict__ st) {
   const int64_t k = st->k2;
   if (k == 0) return;
-  // X is updated at the last block of each group of three and at the block
-  // where the iteration stops; f0 is the first block of the group.
-  const bool finishing = st->reason == REASON_FINISHED;
-  const bool upd_x = finishing || (k % 3 == 0);
-  const int64_t f0 = k - (k - 1) % 3;
-  __shared__ T sA[P * P], sB[P * P], sRa[P * P], sRb[P * P], sRc[P * P], sBc[MAXB * P];
-  __shared__ T sZ[3][P * P];  // Z of blocks k-2, k-1, k
+  constexpr int R = ring_len(P);
+  __shared__ T sA[P * P], sB[P * P], sBc[MAXB * P];
   for (int e = threadIdx.x; e < P * P; e += WG) {
     const int r = e / P, c = e % P, o = r * MAXP + c;
     sA[e] = (T)st->P2A[o];
     sB[e] = (T)st->P2B[o];
-    sRa[e] = (T)st->Ra[o];
-    sRb[e] = (T)st->Rb[o];
-    sRc[e] = (T)st->Rc[o];
-    for (int d = 0; d < 3; ++d) sZ[d][e] = (T)st->Z[(k + 1 + d) % 3][o];
   }
   for (int e = threadIdx.x; e < MAXB * P; e += WG) sBc[e] = (T)st->bcoef[(e / P) * MAXP + (e % P)];
   __syncthreads();
-  const int lstar = st->lstar, nb = st->nb, taken = st->taken;
-  const T* __restrict__ V = Vbase + (size_t)(k % 3) * slot;
-  T* __restrict__ Wn = Vbase + (size_t)((k + 1) % 3) * slot;
-  const T* __restrict__ Mm2 = Mbase + (size_t)((k + 1) % 3) * slot;  // M_{k-2}
-  const T* __restrict__ Mm1 = Mbase + (size_t)((k + 2) % 3) * slot;  // M_{k-1}
-  T* __restrict__ Mk = Mbase + (size_t)(k % 3) * slot;
+  const int nb = st->nb, taken = st->taken;
+  const T* __restrict__ V = Vbase + (size_t)(k % R) * slot;
+  T* __restrict__ Wn = Vbase + (size_t)((k + 1) % R) * slot;
 
   const int64_t stride = (int64_t)gridDim.x * WG;
   for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
     // re-read the coefficients from LDS in every row rather than holding
-    // 6p^2 of them in registers for the whole loop
+    // them in registers for the whole loop
     asm volatile("" ::: "memory");
     T v[P], w[P];
 #pragma unroll
@@ -91,71 +76,71 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
     for (int c = 0; c < P; ++c) Wn[row * P + c] = w[c];
     // keep the unused substitutes orthogonal to the new basis vectors
     for (int b = taken; b < nb; ++b) {
-      T g = bench[row * nb + b];
+      T gv = bench[row * nb + b];
 #pragma unroll
-      for (int l = 0; l < P; ++l) g = fma(-w[l], sBc[b * P + l], g);
-      bench[row * nb + b] = g;
+      for (int l = 0; l < P; ++l) gv = fma(-w[l], sBc[b * P + l], gv);
+      bench[row * nb + b] = gv;
     }
+  }
+}
+
+// The search directions of a group of m blocks g+1 .. g+m (g + m = kexp)
+// into X, and the two search-direction blocks the next group starts from:
+//     X += sum_t V_{g+1+t} Y[0][t] + M_g Y[0][M_g] + M_{g-1} Y[0][M_{g-1}],
+//     M_{g+m-1}, M_{g+m} likewise with Y[1], Y[2] (in place of M_{g-1}, M_g).
+// One row per lane; each input row is read once and feeds all three outputs.
+// The flush holds three p-wide accumulators per lane; for p > 8 it asks for
+// three wavefronts per SIMD (unbounded, p = 16 took all 256 registers).
+constexpr int flush_waves(int p) { return p <= 8 ? 1 : 3; }
+
+template <int P, typename T>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(P)))) void k_flush(const T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
+                                              T* __restrict__ X, int64_t n, int64_t kexp,
+                                              const DevState* __restrict__ st) {
+  if (st->flush_block != kexp || st->flush_len == 0) return;
+  constexpr int S = group_len(P), R = ring_len(P);
+  const int m = st->flush_len;
+  const bool keep_m = st->flush_keep != 0;
+  const int64_t g = kexp - m;
+  __shared__ T sY[3][S + 2][P * P];  // input blocks: V_{g+1+t} at t < m, M_g at S, M_{g-1} at S + 1
+  for (int e = threadIdx.x; e < 3 * (S + 2) * P * P; e += WG) {
+    const int o = e / ((S + 2) * P * P), b = (e / (P * P)) % (S + 2), rc = e % (P * P);
+    const int src = b < S ? b : MAXS + (b - S);
+    sY[o][b][rc] = (b < m || b >= S) ? (T)st->Y[o][src][(rc / P) * MAXP + rc % P] : T(0);
+  }
+  __syncthreads();
+  T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
+  T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
     asm volatile("" ::: "memory");
-    // search directions of the block
-    T mk[P], m2[P], m1[P];
-    {
+    T acc[3][P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      acc[0][c] = X[row * P + c];
+      acc[1][c] = acc[2][c] = T(0);
+    }
+    auto add = [&](const T* __restrict__ src, int b) __attribute__((always_inline)) {
+      T x[P];
+#pragma unroll
+      for (int c = 0; c < P; ++c) x[c] = src[row * P + c];
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+#pragma unroll
+        for (int o = 0; o < 3; ++o)
+#pragma unroll
+          for (int c = 0; c < P; ++c) acc[o][c] = fma(x[r], sY[o][b][r * P + c], acc[o][c]);
+    };
+    for (int t = 0; t < m; ++t) add(Vbase + (size_t)((g + 1 + t) % R) * slot, t);
+    add(Mb, S);
+    add(Ma, S + 1);
+#pragma unroll
+    for (int c = 0; c < P; ++c) X[row * P + c] = acc[0][c];
+    if (keep_m) {
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        m2[c] = Mm2[row * P + c];
-        m1[c] = Mm1[row * P + c];
-        mk[c] = T(0);
-      }
-#pragma unroll
-      for (int l = 0; l < P; ++l) {
-        if (l < lstar) {
-          T m = v[l];
-#pragma unroll
-          for (int r = 0; r < P; ++r)
-            if (r >= l) m = fma(-sRa[r * P + l], m2[r], m);
-#pragma unroll
-          for (int r = 0; r < P; ++r) m = fma(-sRb[r * P + l], m1[r], m);
-#pragma unroll
-          for (int r = 0; r < l; ++r) m = fma(-sRc[r * P + l], mk[r], m);
-          mk[l] = m / sRc[l * P + l];
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < P; ++c) Mk[row * P + c] = mk[c];
-    asm volatile("" ::: "memory");
-    // progressive update of the iterate: the pending blocks of the group,
-    // oldest first (M_{k-2}, M_{k-1} are complete blocks, M_k has l* columns)
-    if (upd_x) {
-      // for p > 8 a few columns at a time, so that the row of X does not
-      // sit in registers next to the three rows of M
-      constexpr int XC = P <= 8 ? P : (P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1));
-#pragma unroll
-      for (int c0 = 0; c0 < P; c0 += XC) {
-        T x[XC];
-#pragma unroll
-        for (int c = 0; c < XC; ++c) x[c] = X[row * P + c0 + c];
-        if (f0 <= k - 2) {
-#pragma unroll
-          for (int l = 0; l < P; ++l)
-#pragma unroll
-            for (int c = 0; c < XC; ++c) x[c] = fma(m2[l], sZ[0][l * P + c0 + c], x[c]);
-        }
-        if (f0 <= k - 1) {
-#pragma unroll
-          for (int l = 0; l < P; ++l)
-#pragma unroll
-            for (int c = 0; c < XC; ++c) x[c] = fma(m1[l], sZ[1][l * P + c0 + c], x[c]);
-        }
-#pragma unroll
-        for (int l = 0; l < P; ++l) {
-          if (l < lstar) {
-#pragma unroll
-            for (int c = 0; c < XC; ++c) x[c] = fma(mk[l], sZ[2][l * P + c0 + c], x[c]);
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < XC; ++c) X[row * P + c0 + c] = x[c];
+        Ma[row * P + c] = acc[1][c];
+        Mb[row * P + c] = acc[2][c];
       }
     }
   }
@@ -318,12 +303,21 @@ static int stream_grid(int64_t n) {
   }
 
 template <typename T>
-hipError_t launch_pass2(int p, T* Vbase, T* Mbase, size_t slot, T* X, T* bench, int64_t n, DevState* st,
-                        hipStream_t s) {
+hipError_t launch_pass2(int p, T* Vbase, size_t slot, T* bench, int64_t n, DevState* st, hipStream_t s) {
   const int g = stream_grid(n);
-#define L4(P) hipLaunchKernelGGL((k_pass2<P, T>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, bench, n, st)
+#define L4(P) hipLaunchKernelGGL((k_pass2<P, T>), dim3(g), dim3(WG), 0, s, Vbase, slot, bench, n, st)
   BMR_DISPATCH_P(p, L4)
 #undef L4
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot, T* X, int64_t n, int64_t k, const DevState* st,
+                        hipStream_t s) {
+  const int g = stream_grid(n);
+#define L5(P) hipLaunchKernelGGL((k_flush<P, T>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, n, k, st)
+  BMR_DISPATCH_P(p, L5)
+#undef L5
   return hipGetLastError();
 }
 
@@ -392,7 +386,8 @@ hipError_t launch_pattern_grad(int p, const bmr_csr_t& A, const double* Lam, con
 }
 
 #define BMR_INSTANTIATE(T)                                                                                          \
-  template hipError_t launch_pass2<T>(int, T*, T*, size_t, T*, T*, int64_t, DevState*, hipStream_t);               \
+  template hipError_t launch_pass2<T>(int, T*, size_t, T*, int64_t, DevState*, hipStream_t);                        \
+  template hipError_t launch_flush<T>(int, const T*, T*, size_t, T*, int64_t, int64_t, const DevState*, hipStream_t); \
   template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                                  \
   template hipError_t launch_bench_init<T>(T*, int64_t, int, uint64_t, hipStream_t);                               \
   template hipError_t launch_coldots<T>(const T*, int, int, const T*, int, int, int64_t, double*, int, hipStream_t); \

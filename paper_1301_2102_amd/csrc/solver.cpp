@@ -71,7 +71,7 @@ struct Run {
   size_t slot;
   std::vector<double> hpart;
 
-  T* Vslot(int64_t k) { return V + (size_t)(k % 3) * slot; }
+  T* Vslot(int64_t k) { return V + (size_t)(k % ring_len(p)) * slot; }
 
   // Column sums of k_coldots, summed on the host in workgroup order.
   template <typename U>
@@ -184,9 +184,9 @@ Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int p
   off = align256(off + (mixed ? 0 : sizeof(double) * (size_t)hist_cap * p));
   const size_t se = slot_elems(n, p);
   L.off_V = off;
-  off = align256(off + esz * 3 * se);
+  off = align256(off + esz * ring_len(p) * se);
   L.off_M = off;
-  off = align256(off + esz * 3 * se);
+  off = align256(off + esz * 2 * se);
   L.off_bench = off;
   off = align256(off + esz * (size_t)n * nb);
   if (mixed) {
@@ -257,8 +257,8 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   const int p = r.p, nb = r.nb;
   const int64_t n = r.n;
   // ---- set-up -------------------------------------------------------------
-  HIP_TRY(launch_fill<T>(r.V, 3 * r.slot, T(0), r.s));
-  HIP_TRY(launch_fill<T>(r.M, 3 * r.slot, T(0), r.s));
+  HIP_TRY(launch_fill<T>(r.V, ring_len(p) * r.slot, T(0), r.s));
+  HIP_TRY(launch_fill<T>(r.M, 2 * r.slot, T(0), r.s));
   HIP_TRY(launch_fill<T>(X, (size_t)n * p, T(0), r.s));
   HIP_TRY(launch_bench_init<T>(r.bench, n, nb, o.seed, r.s));
 
@@ -374,9 +374,19 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     return 0;
   };
 
-  // enqueue `batch` block iterations, then a copy of the status record
+  // Enqueue `batch` block iterations, then a copy of the status record.
+  // Every enqueued iteration is block kq of the device loop unless the loop
+  // has halted (then its kernels return at once), so the host knows which
+  // iterations end a group of search directions and enqueues the flush
+  // after them; the flush checks the block number the band kernel recorded.
+  const int grp = group_len(p);
+  int64_t kq = 1;
+  auto flush = [&](int64_t kb) -> int {
+    HIP_TRY(launch_flush<T>(r.p, r.V, r.M, r.slot, X, r.n, kb, r.st, r.s));
+    return 0;
+  };
   auto enq = [&](int slot) -> int {
-    for (int q = 0; q < batch; ++q) {
+    for (int q = 0; q < batch; ++q, ++kq) {
       if (prof) HIP_TRY(hipEventRecord(pev[slot][0], r.s));
       HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][1], r.s));
@@ -384,13 +394,15 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
       if (prof) HIP_TRY(hipEventRecord(pev[slot][2], r.s));
       HIP_TRY(launch_band(r.p, 0, r.red, r.hist, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][3], r.s));
-      HIP_TRY(launch_pass2<T>(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
+      HIP_TRY(launch_pass2<T>(r.p, r.V, r.slot, r.bench, r.n, r.st, r.s));
+      if (kq % grp == 0) TRY(flush(kq));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][4], r.s));
     }
     HIP_TRY(hipMemcpyAsync(&pin[slot], r.st, sizeof(Ctl), hipMemcpyDeviceToHost, r.s));
     HIP_TRY(hipEventRecord(ev[slot], r.s));
     return 0;
   };
+  int64_t last_explicit = 0;  // block of the last column-wise QR (its flush is enqueued with it)
   for (;;) {
     TRY(enq(0));
     int cur = 0;
@@ -433,11 +445,20 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     hs->reason = REASON_NONE;
     HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
     HIP_TRY(launch_band(r.p, 1, r.red, r.hist, r.st, r.s));
-    HIP_TRY(launch_pass2<T>(r.p, r.V, r.M, r.slot, X, r.bench, r.n, r.st, r.s));
+    HIP_TRY(launch_pass2<T>(r.p, r.V, r.slot, r.bench, r.n, r.st, r.s));
+    TRY(flush(k));
+    last_explicit = k;
+    kq = k + 1;
     HIP_TRY(hipStreamSynchronize(r.s));
   }
   HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
   HIP_TRY(hipStreamSynchronize(r.s));
+  // a stop inside a group: its search directions still go into X
+  if (hs->reason == REASON_FINISHED && hs->flush_len > 0 && hs->flush_block % grp != 0 &&
+      hs->flush_block != last_explicit) {
+    TRY(flush(hs->flush_block));
+    HIP_TRY(hipStreamSynchronize(r.s));
+  }
   if (res_hist && o.hist_cap > 0) {
     const int64_t rows = std::min<int64_t>(hs->j, o.hist_cap);
     if (rows > 0)
