@@ -36,9 +36,12 @@ def kernel_bytes(A, p, nb, esz=8):
     n, nnz = A.n, A.nnz
     blk = esz * n * p
     pass1 = (4 + esz) * nnz + 4 * (n + 1) + 3 * blk + esz * n * nb   # A, V_k, V_{k-1}, W out, bench in
-    # W, V_k, V_{k+1}, M_{k-2}, M_{k-1}, M_k every block iteration, X read and
-    # written once per three block iterations, the bench in and out
-    pass2 = 6 * blk + (2 * blk) // 3 + 2 * esz * n * nb
+    # pass 2: W, V_k in, V_{k+1} out and the bench in and out every block
+    # iteration; the flush once per group of s blocks: the group's s Lanczos
+    # blocks, M_g, M_{g-1} and X in, X and the next group's two M blocks out
+    from paper_1301_2102_amd import group_len
+    s = group_len(p)
+    pass2 = 3 * blk + 2 * esz * n * nb + ((s + 6) * blk) // s
     spmm = (4 + esz) * nnz + 4 * (n + 1) + 2 * blk                   # A, V in, W out
     return {"pass1_spmm_gram": pass1, "pass2_update": pass2, "spmm": spmm}
 

@@ -20,6 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libbmr.so")
 MAX_P = 16
 MAX_BENCH = 4
 
+
+def group_len(p: int) -> int:
+    """Blocks per group of search directions (the library applies eq. (4.2)
+    once per group): min(16, max(2, 1024 // p^2)), as in the library."""
+    return min(16, max(2, 1024 // (p * p)))
+
 CONVERGED = 0
 MAX_ITER = 1
 BENCH_EXHAUSTED = 2

@@ -20,7 +20,7 @@ constexpr int STATUS_RUNNING = 100;
 // search-direction blocks before the group.  s is capped so that the
 // 3 (s + 2) p x p coefficient blocks of a group fit in LDS.  V_k lives in
 // slot k mod ring_len(p) of the V ring.
-constexpr int MAXS = 12;
+constexpr int MAXS = 16;
 __host__ __device__ constexpr int group_len(int p) {
   return 1024 / (p * p) > MAXS ? MAXS : (1024 / (p * p) < 2 ? 2 : 1024 / (p * p));
 }

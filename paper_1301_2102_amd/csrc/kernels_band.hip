@@ -83,7 +83,8 @@ struct BandShared {
     };
     struct {  // phase B: R rows of blocks k-2, k-1, k in the block's columns, Z_k, C, D, E
       double Ra[P][P], Rb[P][P], Rc[P][P], Zk[P][P], C[P][P], D[P][P], E[P][P];
-      double Tr[3][P][P];  // backward recurrence of the group coefficients (ring)
+      double Tr[3][3][P][P];                 // backward recurrences of the three outputs (ring of 3)
+      double gs[4][group_len(P)][P][P];      // the group's C, D, E, Z at the flush
     };
   };
   double araw[P], beta[P];
@@ -283,51 +284,99 @@ __device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh
   }
   wave_sync();
   if (!finishing && t != S - 1) return;
-  // coefficients of positions u < t come from the earlier band kernels of
-  // the group, those of position t from LDS
-  auto cC = [&](int u, int r, int c) { return u == t ? sh.C[r][c] : st->gC[u][r * MAXP + c]; };
-  auto cD = [&](int u, int r, int c) { return u == t ? sh.D[r][c] : st->gD[u][r * MAXP + c]; };
-  auto cE = [&](int u, int r, int c) { return u == t ? sh.E[r][c] : st->gE[u][r * MAXP + c]; };
-  auto cZ = [&](int u, int r, int c) { return u == t ? sh.Zk[r][c] : st->gZ[u][r * MAXP + c]; };
+  // stage the group's coefficients in LDS: positions u < t from the earlier
+  // band kernels of the group, in batches whose loads are all in flight
+  // before the first is stored (a single wavefront would otherwise wait for
+  // each load in turn), and position t from this one
+  {
+    constexpr int EL = (P * P + 63) / 64;             // elements per lane and matrix
+    constexpr int BATCH = 32 / (4 * EL) > 0 ? 32 / (4 * EL) : 1;
+#pragma unroll 1
+    for (int u0 = 0; u0 < t; u0 += BATCH) {
+      double buf[BATCH][4][EL];
+#pragma unroll
+      for (int du = 0; du < BATCH; ++du)
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+          for (int x = 0; x < EL; ++x) {
+            const int u = u0 + du, e = tid + 64 * x;
+            const double* src = w == 0 ? st->gC[u] : w == 1 ? st->gD[u] : w == 2 ? st->gE[u] : st->gZ[u];
+            buf[du][w][x] = (u < t && e < P * P) ? src[(e / P) * MAXP + e % P] : 0.0;
+          }
+#pragma unroll
+      for (int du = 0; du < BATCH; ++du)
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+          for (int x = 0; x < EL; ++x) {
+            const int u = u0 + du, e = tid + 64 * x;
+            if (u < t && e < P * P) sh.gs[w][u][e / P][e % P] = buf[du][w][x];
+          }
+    }
+  }
+  for (int e = tid; e < P * P; e += 64) {
+    const int r = e / P, c = e % P;
+    sh.gs[0][t][r][c] = sh.C[r][c];
+    sh.gs[1][t][r][c] = sh.D[r][c];
+    sh.gs[2][t][r][c] = sh.E[r][c];
+    sh.gs[3][t][r][c] = sh.Zk[r][c];
+  }
+  wave_sync();
+  auto cC = [&](int u, int r, int c) { return sh.gs[0][u][r][c]; };
+  auto cD = [&](int u, int r, int c) { return sh.gs[1][u][r][c]; };
+  auto cE = [&](int u, int r, int c) { return sh.gs[2][u][r][c]; };
+  auto cZ = [&](int u, int r, int c) { return sh.gs[3][u][r][c]; };
   const int m = t + 1;
-  const int nout = finishing ? 1 : 3;
+  // the three outputs' recurrences run side by side (one element of each
+  // per lane and step), which hides the latency of their dependent chains
+  constexpr int NE = 3 * P * P, IT = (NE + 63) / 64;
 #pragma unroll 1
-  for (int o = 0; o < nout; ++o) {
-#pragma unroll 1
-    for (int u = m - 1; u >= 0; --u) {
-      const int s0 = u % 3, s1 = (u + 1) % 3, s2 = (u + 2) % 3;
-      for (int e = tid; e < P * P; e += 64) {
-        const int q = e / P, c = e % P;
+  for (int u = m - 1; u >= 0; --u) {
+    const int s0 = u % 3, s1 = (u + 1) % 3, s2 = (u + 2) % 3;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + 64 * it;
+      if (e < NE) {
+        const int o = e / (P * P), q = (e / P) % P, c = e % P;
         double v = (o == 0) ? cZ(u, q, c) : ((u == m - 3 + o && q == c) ? 1.0 : 0.0);
         if (u + 1 < m)
-          for (int i = 0; i < P; ++i) v += cD(u + 1, q, i) * sh.Tr[s1][i][c];
+          for (int i = 0; i < P; ++i) v += cD(u + 1, q, i) * sh.Tr[o][s1][i][c];
         if (u + 2 < m)
-          for (int i = 0; i < P; ++i) v += cE(u + 2, q, i) * sh.Tr[s2][i][c];
-        sh.Tr[s0][q][c] = v;
+          for (int i = 0; i < P; ++i) v += cE(u + 2, q, i) * sh.Tr[o][s2][i][c];
+        sh.Tr[o][s0][q][c] = v;
       }
-      wave_sync();
-      for (int e = tid; e < P * P; e += 64) {
-        const int q = e / P, c = e % P;
+    }
+    wave_sync();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + 64 * it;
+      if (e < NE) {
+        const int o = e / (P * P), q = (e / P) % P, c = e % P;
         double y = 0.0;
-        for (int r = q; r < P; ++r) y += cC(u, q, r) * sh.Tr[s0][r][c];
+        for (int r = q; r < P; ++r) y += cC(u, q, r) * sh.Tr[o][s0][r][c];
         st->Y[o][u][q * MAXP + c] = y;
       }
-      wave_sync();
-    }
-    for (int e = tid; e < P * P; e += 64) {
-      const int q = e / P, c = e % P;
-      double yb = 0.0, ya = 0.0;
-      for (int i = 0; i < P; ++i) {
-        yb += cD(0, q, i) * sh.Tr[0][i][c];
-        ya += cE(0, q, i) * sh.Tr[0][i][c];
-      }
-      if (m >= 2)
-        for (int i = 0; i < P; ++i) yb += cE(1, q, i) * sh.Tr[1][i][c];
-      st->Y[o][MAXS][q * MAXP + c] = yb;
-      st->Y[o][MAXS + 1][q * MAXP + c] = ya;
     }
     wave_sync();
   }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = tid + 64 * it;
+    if (e < NE) {
+      const int o = e / (P * P), q = (e / P) % P, c = e % P;
+      double yb = 0.0, ya = 0.0;
+      for (int i = 0; i < P; ++i) {
+        yb += cD(0, q, i) * sh.Tr[o][0][i][c];
+        ya += cE(0, q, i) * sh.Tr[o][0][i][c];
+      }
+      if (m >= 2)
+        for (int i = 0; i < P; ++i) yb += cE(1, q, i) * sh.Tr[o][1][i][c];
+      st->Y[o][MAXS][q * MAXP + c] = yb;
+      st->Y[o][MAXS + 1][q * MAXP + c] = ya;
+    }
+  }
+  wave_sync();
   if (tid == 0) {
     st->flush_len = m;
     st->flush_keep = finishing ? 0 : 1;
