@@ -120,20 +120,37 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
       acc[0][c] = X[row * P + c];
       acc[1][c] = acc[2][c] = T(0);
     }
-    auto add = [&](const T* __restrict__ src, int b) __attribute__((always_inline)) {
-      T x[P];
+    // inputs i = 0 .. m + 1: V_{g+1+i} (i < m), M_g, M_{g-1}.  For p <= 8
+    // the loads of four input rows are issued before their FMAs, so that a
+    // lane has several loads in flight (0.71 -> 0.63 ms per group at 128^3,
+    // p = 8); at larger p one row at a time keeps the registers in bounds.
+    constexpr int U = P <= 8 ? 4 : 1;
+    for (int i0 = 0; i0 < m + 2; i0 += U) {
+      T x[U][P];
 #pragma unroll
-      for (int c = 0; c < P; ++c) x[c] = src[row * P + c];
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u;
+        if (i < m + 2) {
+          const T* __restrict__ src =
+              i < m ? Vbase + (size_t)((g + 1 + i) % R) * slot : (i == m ? Mb : Ma);
 #pragma unroll
-      for (int r = 0; r < P; ++r)
+          for (int c = 0; c < P; ++c) x[u][c] = src[row * P + c];
+        }
+      }
 #pragma unroll
-        for (int o = 0; o < 3; ++o)
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u;
+        if (i < m + 2) {
+          const int b = i < m ? i : S + (i - m);
 #pragma unroll
-          for (int c = 0; c < P; ++c) acc[o][c] = fma(x[r], sY[o][b][r * P + c], acc[o][c]);
-    };
-    for (int t = 0; t < m; ++t) add(Vbase + (size_t)((g + 1 + t) % R) * slot, t);
-    add(Mb, S);
-    add(Ma, S + 1);
+          for (int r = 0; r < P; ++r)
+#pragma unroll
+            for (int o = 0; o < 3; ++o)
+#pragma unroll
+              for (int c = 0; c < P; ++c) acc[o][c] = fma(x[u][r], sY[o][b][r * P + c], acc[o][c]);
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < P; ++c) X[row * P + c] = acc[0][c];
     if (keep_m) {

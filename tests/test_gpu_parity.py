@@ -117,6 +117,23 @@ def test_stop_inside_a_block(stop):
     assert _relcols(X, ro.X) <= 1e-10
 
 
+@pytest.mark.parametrize("p,stops", [(4, [63, 64, 65, 127, 128, 129, 191]), (8, [127, 128, 129, 136]),
+                                     (16, [63, 64, 65, 80])])
+def test_stop_at_group_boundaries(p, stops):
+    """The search directions enter X once per group of group_len(p) blocks
+    (16 at p <= 8, 4 at p = 16) and where the iteration stops: stops at a
+    group's last block (its regular flush), inside it, and just after it
+    (the flush of a partial group) give the oracle's iterate."""
+    s = bmr.group_len(p)
+    A = laplacian((10, 11, 12), 0.3)
+    B = rhs_normal(A.n, p, seed=11 + p)
+    for stop in stops:
+        X, info, ro, _ = _both(A, B, 1e-30, stop)
+        assert info.band_iters == ro.iters == stop
+        assert info.block_iters == -(-stop // p)
+        assert _relcols(X, ro.X) <= 1e-8, (stop, s)
+
+
 def test_dependence_e1_ae1_in_iteration():
     """B = [e_1, A e_1]: the first candidate is dependent (column-wise QR path,
     bench substitution); column 2 is solved exactly by x = e_1."""
