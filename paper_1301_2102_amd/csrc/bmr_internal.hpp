@@ -115,7 +115,11 @@ struct Layout {
 };
 
 Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision);
-int pass1_grid(int64_t n, int p);
+int pass1_grid(int64_t n, int p);  // the most pass-1 workgroups (sizes the partial sums)
+// The pass-1 workgroups of a solve in storage type T: one resident round on
+// the current device, at most pass1_grid(n, p).
+template <typename T>
+int pass1_resident_grid(int64_t n, int p);
 
 // ---- launch wrappers (kernels_*.hip) ------------------------------------
 // T = double (FP64 solve) or float (inner solve of the mixed-precision solver);

@@ -721,6 +721,49 @@ int pass1_grid(int64_t n, int p) {
   return (int)g;
 }
 
+template <typename T>
+int pass1_resident_grid(int64_t n, int p) {
+  // One round of workgroups: as many as the device holds at once
+  // (occupancy x compute units), at most pass1_grid(n, p).  A second,
+  // partial round left a tail (at 128^3 against 2048 workgroups: p = 8 FP32
+  // 0.106 -> 0.100 ms, p = 16 FP64 0.441 -> 0.395 ms).  With one lane per
+  // row (p <= 2) two rounds measured faster (p = 1: 0.074 against
+  // 0.079 ms), so those keep pass1_grid.
+  const int g = pass1_grid(n, p);
+  if (layout_cpl(p) == p) return g;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return g;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return g;
+  hipError_t e = hipErrorInvalidValue;
+#define OC(P) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_pass1<P, T>), WG, 0)
+  switch (p) {
+    case 1: OC(1); break;
+    case 2: OC(2); break;
+    case 3: OC(3); break;
+    case 4: OC(4); break;
+    case 5: OC(5); break;
+    case 6: OC(6); break;
+    case 7: OC(7); break;
+    case 8: OC(8); break;
+    case 9: OC(9); break;
+    case 10: OC(10); break;
+    case 11: OC(11); break;
+    case 12: OC(12); break;
+    case 13: OC(13); break;
+    case 14: OC(14); break;
+    case 15: OC(15); break;
+    case 16: OC(16); break;
+    default: break;
+  }
+#undef OC
+  if (e != hipSuccess || per < 1 || cus < 1) return g;
+  const int64_t resident = (int64_t)per * cus;
+  return (int)std::min<int64_t>(g, resident);
+}
+template int pass1_resident_grid<double>(int64_t, int);
+template int pass1_resident_grid<float>(int64_t, int);
+
 static int spmm_grid(int64_t n, int p) {
   // one workgroup step each: a grid that walks longer row ranges with the
   // pass-1 pipeline measured slower for the plain product

@@ -478,7 +478,7 @@ void bind(Run<T>& r, const bmr_csr_t* A, const T* val, int p, int nb, hipStream_
   r.nb = nb;
   r.n = A->n;
   r.s = s;
-  r.n_wg = L.n_wg;
+  r.n_wg = pass1_resident_grid<T>(A->n, p);  // <= L.n_wg, which sizes the partial sums
   r.st = (DevState*)(ws + L.off_state);
   r.red = (double*)(ws + L.off_red);
   r.part = (double*)(ws + L.off_part);
