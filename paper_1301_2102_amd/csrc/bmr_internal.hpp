@@ -133,7 +133,7 @@ hipError_t launch_residual(int p, const bmr_csr_t& A, const double* B, const dou
                            double* part, int n_wg, hipStream_t s);
 hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, DevState* st, int check_halt,
                          hipStream_t s);
-hipError_t launch_band(int p, int mode, const double* red, double* hist, DevState* st, hipStream_t s);
+hipError_t launch_band(int p, int mode, int nb, const double* red, double* hist, DevState* st, hipStream_t s);
 template <typename T>
 hipError_t launch_pass2(int p, T* Vbase, size_t slot_elems, T* bench, int64_t n, DevState* st, hipStream_t s);
 // The group's search directions into X (and the next group's two M blocks);

@@ -19,12 +19,13 @@
 // route cannot resolve the dependence test (Section 5) and the host runs the
 // new-block QR column by column instead.
 //
-// Work split inside the wavefront: lane l owns column l of the block (its
-// 4p band entries, kept in LDS) and column l of the S-hat window.  The
-// rotations of the two previous blocks are applied by all lanes at once; the
-// p rotations of each column of the block are generated together (lane t
-// makes rotation t from a prefix sum of squares) and applied by the lanes
-// owning the columns to its right.
+// Work split: lane l owns column l of the block (its 4p band entries, kept
+// in LDS, with a window of p+1 of them in registers) and column l of the
+// S-hat window.  A second wavefront applies the rotations of the two
+// previous blocks while the first is in phase A; the p rotations of each
+// column of the block are generated together (lane t makes rotation t from a
+// prefix sum of squares) and applied by the lanes owning the columns to its
+// right.
 #include <math.h>
 
 #include "bmr_internal.hpp"
@@ -60,10 +61,73 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Barrier of the band kernel's two wavefronts that orders their LDS accesses
+// only: the global stores still in flight are not waited for.
+__device__ inline void wg_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Givens rotation of the pair (x, y).  In a sweep x passes through p
+// rotations in a row, so the products with y are formed first and x enters
+// each result through a single fused multiply-add.
 __device__ inline void rotate(double c, double s, double& x, double& y) {
   const double a = x, b = y;
-  x = c * a + s * b;
-  y = -s * a + c * b;
+  x = fma(c, a, s * b);
+  y = fma(-s, a, c * b);
+}
+
+// Cross-lane moves inside a row of 16 lanes by DPP, which reads the other
+// lane's register directly instead of going through the LDS.  Controls:
+// 0xB1 and 0x4E swap neighbours at distance 1 and 2 inside each group of 4,
+// 0x141 mirrors each half row, 0x140 the row, 0x110 + o shifts the row
+// right by o (lanes below o receive 0).
+template <int CTRL>
+__device__ inline int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ inline double dpp_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_int<CTRL>((int)b), hi = dpp_int<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// largest value over the 16 lanes of each row, in every lane of the row
+__device__ inline double row_max(double v) {
+  v = fmax(v, dpp_double<0xB1>(v));
+  v = fmax(v, dpp_double<0x4E>(v));
+  v = fmax(v, dpp_double<0x141>(v));
+  return fmax(v, dpp_double<0x140>(v));
+}
+
+// the value of lane (l - o) of the same row in lane l, 0 where l - o falls
+// outside it; o is a constant power of two below 16 after unrolling
+template <typename T>
+__device__ inline T row_shr(T v, int o) {
+  if constexpr (sizeof(T) == 8) {
+    switch (o) {
+      case 1: return dpp_double<0x111>(v);
+      case 2: return dpp_double<0x112>(v);
+      case 4: return dpp_double<0x114>(v);
+      default: return dpp_double<0x118>(v);
+    }
+  } else {
+    switch (o) {
+      case 1: return dpp_int<0x111>(v);
+      case 2: return dpp_int<0x112>(v);
+      case 4: return dpp_int<0x114>(v);
+      default: return dpp_int<0x118>(v);
+    }
+  }
+}
+
+// lane l's value, the same in every lane
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ void halt_with(DevState* st, int status, int reason) {
@@ -97,29 +161,94 @@ struct BandShared {
   int flag;
 };
 
-// Phase A: A_k, Gram of the remainder, Cholesky -> B_k, bench coefficients.
-// Returns false (the same in every lane) when the column-wise QR must take
-// over.  Leaves A_k and B_k in shared memory.
+// Scalars of the state the band kernel reads, loaded once at its start.
+struct BandCtl {
+  int64_t k, j0, max_iter, hist_cap;
+  int halt, lcap, cap_status, taken;
+  double tol, tau_fb;
+};
+
+// Every global input of the band kernel, loaded into registers before the
+// first of them is used.  A single wavefront would otherwise wait for each
+// load in turn, and, since loads and stores share one counter, for every
+// store issued before it.  The rotations of all three ring slots are read so
+// that no load waits for k.
 template <int P>
-__device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ st, BandShared<P>& sh) {
+struct BandLoads {
+  static constexpr int N = (P * P + 63) / 64;      // entries of a p x p matrix per lane
+  static constexpr int NW = (P * MAXB + 63) / 64;  // entries of W^T g (or V^T g) per lane
+  double bprev[N], rot[3][2][N], shat[N], m0[N], m1[N], m2[N], wg[NW], vg[NW];
+  double a, beta;
+};
+
+template <int P>
+__device__ __attribute__((always_inline)) inline void load_band(int mode, int nb, const double* __restrict__ red, const DevState* __restrict__ st,
+                                 BandCtl& c, BandLoads<P>& L) {
+  using BL = BandLoads<P>;
   const int tid = threadIdx.x;
-  const int nb = st->nb, taken = st->taken;
-  for (int e = tid; e < P * P; e += 64) {
-    sh.G[e] = red[off_G(P) + e];
-    sh.Q[e] = red[off_Q(P) + e];
-    sh.Pm[e] = red[off_P(P) + e];
+  c.halt = st->halt;
+  c.k = st->k;
+  c.j0 = st->j;
+  c.max_iter = st->max_iter;
+  c.hist_cap = st->hist_cap;
+  c.lcap = st->lcap;
+  c.cap_status = st->cap_status;
+  c.taken = st->taken;
+  c.tol = st->tol;
+  c.tau_fb = st->tau_fb;
+#pragma unroll
+  for (int x = 0; x < BL::N; ++x) {
+    const int e = tid + 64 * x;
+    const bool ok = e < P * P;
+    const int r = ok ? e / P : 0, cc = ok ? e % P : 0, o = r * MAXP + cc;
+    L.bprev[x] = ok ? st->Bprev[o] : 0.0;
+    L.shat[x] = ok ? st->Shat[o] : 0.0;
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      L.rot[sl][0][x] = ok ? st->rot[sl][r][cc][0] : 1.0;
+      L.rot[sl][1][x] = ok ? st->rot[sl][r][cc][1] : 0.0;
+    }
+    if (mode == 0) {  // Gram products of pass 1
+      const int ei = ok ? e : 0;
+      L.m0[x] = ok ? red[off_G(P) + ei] : 0.0;
+      L.m1[x] = ok ? red[off_Q(P) + ei] : 0.0;
+      L.m2[x] = ok ? red[off_P(P) + ei] : 0.0;
+    } else {  // A_k and B_k from the column-wise QR
+      L.m0[x] = ok ? st->Ak[o] : 0.0;
+      L.m1[x] = ok ? st->Bk[o] : 0.0;
+      L.m2[x] = 0.0;
+    }
   }
-  for (int e = tid; e < P * nb; e += 64) {
-    sh.Wg[e] = red[off_Wg(P) + e];
-    sh.Vg[e] = red[off_Vg(P, nb) + e];
+#pragma unroll
+  for (int x = 0; x < BL::NW; ++x) {
+    const int e = tid + 64 * x;
+    const bool ok = mode == 0 && e < P * nb;
+    const int ei = ok ? e : 0;
+    L.wg[x] = ok ? red[off_Wg(P) + ei] : 0.0;
+    L.vg[x] = ok ? red[off_Vg(P, nb) + ei] : 0.0;
   }
-  if (tid < P) sh.araw[tid] = sqrt(red[off_a(P) + tid]);
-  wave_sync();
+  const int lane = tid < P ? tid : 0;
+  L.a = (mode == 0 && tid < P) ? red[off_a(P) + lane] : 0.0;
+  L.beta = tid < P ? st->beta[lane] : 0.0;
+}
+
+// Phase A: A_k (phase_a_ak), then the Gram of the remainder, Cholesky ->
+// B_k, bench coefficients (phase_a).  Returns false (the same in every lane)
+// when the column-wise QR must take over.  Leaves A_k and B_k in shared
+// memory.
+template <int P>
+__device__ void phase_a_ak(BandShared<P>& sh) {
+  const int tid = threadIdx.x;
   for (int e = tid; e < P * P; e += 64) {
     const int r = e / P, c = e % P;
     sh.Ak[r][c] = (r >= c) ? sh.G[r * P + c] : sh.G[c * P + r];
   }
   wave_sync();
+}
+
+template <int P>
+__device__ bool phase_a(int nb, int taken, double tau_fb, DevState* __restrict__ st, BandShared<P>& sh) {
+  const int tid = threadIdx.x;
   for (int e = tid; e < P * P; e += 64) {
     const int l = e / P, m = e % P;
     double t = 0.0, u = 0.0;
@@ -152,7 +281,7 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
   for (int l = 0; l < P; ++l) {
     if (tid == 0) {
       const double d = sh.T2[l][l];
-      const double thr = st->tau_fb * sh.araw[l];
+      const double thr = tau_fb * sh.araw[l];
       const bool ok = (d > 0.0) && isfinite(d) && (sqrt(d) >= thr);
       sh.flag = ok;
       sh.piv = ok ? sqrt(d) : 0.0;
@@ -203,30 +332,58 @@ __device__ bool phase_a(const double* __restrict__ red, DevState* __restrict__ s
   return true;
 }
 
-// Inputs of phase B that phase A does not touch: B_{k-1}, the rotations of
-// blocks k-2 and k-1, the S-hat window and the column norms of B.  Issued
-// first so that their latency overlaps phase A.
+// The inputs, from the registers they were loaded into, to LDS: B_{k-1},
+// the rotations of blocks k-2 and k-1 (ring slots (k-2) mod 3 and (k-1) mod 3;
+// the identity before block 1), the S-hat window, the column norms of B, and
+// either phase A's Gram products (mode 0) or A_k and B_k (mode 1).
 template <int P>
-__device__ void load_band_inputs(const DevState* __restrict__ st, BandShared<P>& sh) {
+__device__ __attribute__((always_inline)) inline void store_band_inputs(int mode, int nb, const BandCtl& ctl,
+                                                                        const BandLoads<P>& L, BandShared<P>& sh) {
   const int tid = threadIdx.x;
-  const int64_t k = st->k;
-  for (int e = tid; e < P * P; e += 64) {
-    const int r = e / P, c = e % P;
-    sh.Bp[r][c] = st->Bprev[r * MAXP + c];
+  const int64_t k = ctl.k;
+  const int s0 = (int)((k + 1) % 3), s1 = (int)((k + 2) % 3);  // (k-2) mod 3, (k-1) mod 3 for k >= 1
+  const bool have0 = k - 2 >= 1, have1 = k - 1 >= 1;
+#pragma unroll
+  for (int x = 0; x < BandLoads<P>::N; ++x) {
+    const int e = tid + 64 * x;
+    if (e < P * P) {
+      const int r = e / P, c = e % P;
+      sh.Bp[r][c] = L.bprev[x];
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const double r0 = L.rot[0][w][x], r1 = L.rot[1][w][x], r2 = L.rot[2][w][x];
+        const double v0 = s0 == 0 ? r0 : s0 == 1 ? r1 : r2;
+        const double v1 = s1 == 0 ? r0 : s1 == 1 ? r1 : r2;
+        const double id = w == 0 ? 1.0 : 0.0;
+        sh.rot[0][r][c][w] = have0 ? v0 : id;
+        sh.rot[1][r][c][w] = have1 ? v1 : id;
+      }
+      // S-hat window, column-major per lane: p live rows, then p zero rows
+      sh.s2[c][r] = L.shat[x];
+      sh.s2[c][P + r] = 0.0;
+      if (mode == 0) {  // phase A's Gram products
+        sh.G[e] = L.m0[x];
+        sh.Q[e] = L.m1[x];
+        sh.Pm[e] = L.m2[x];
+      } else {  // A_k and B_k of the column-wise QR
+        sh.Ak[r][c] = L.m0[x];
+        sh.Bk[r][c] = L.m1[x];
+      }
+    }
   }
-  for (int e = tid; e < 2 * P * P; e += 64) {
-    const int b = e / (P * P), i = (e / P) % P, t = e % P;
-    const int64_t kb = k - 2 + b;  // block whose rotations these are
-    const bool have = kb >= 1;
-    const int rb = have ? (int)(kb % 3) : 0;
-    sh.rot[b][i][t][0] = have ? st->rot[rb][i][t][0] : 1.0;
-    sh.rot[b][i][t][1] = have ? st->rot[rb][i][t][1] : 0.0;
+#pragma unroll
+  for (int x = 0; x < BandLoads<P>::NW; ++x) {
+    const int e = tid + 64 * x;
+    if (mode == 0 && e < P * nb) {
+      sh.Wg[e] = L.wg[x];
+      sh.Vg[e] = L.vg[x];
+    }
   }
-  for (int e = tid; e < 2 * P * P; e += 64) {  // S-hat window, column-major per lane
-    const int q = e / (2 * P), r = e % (2 * P);
-    sh.s2[q][r] = (r < P) ? st->Shat[r * MAXP + q] : 0.0;
+  if (tid < P) {
+    sh.beta[tid] = L.beta;
+    if (mode == 0) sh.araw[tid] = sqrt(L.a);
   }
-  if (tid < P) sh.beta[tid] = st->beta[tid];
+  wave_sync();
 }
 
 // Search directions of block k in the grouped form (eq. (4.1)):
@@ -384,50 +541,106 @@ __device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh
   }
 }
 
-// Phase B: Givens QR of the p new columns of H-bar, S-hat window, residuals,
-// stopping test, coefficients of the search directions and of the X update.
-// Columns live in LDS and the outer loops stay rolled: the kernel runs as a
-// single wavefront, so compact code matters more than register residency.
+// Rotations of the two previous blocks applied to rows 0 .. 3p-1 of the
+// block's columns, which hold only B_{k-1} and A_k: the band kernel's second
+// wavefront runs this while the first is still in phase A.
 template <int P>
-__device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, BandShared<P>& sh) {
-  const int tid = threadIdx.x;
-  const int64_t k = st->k;
-  const int64_t j0 = st->j;
-  const int lcap = st->lcap, cap_status = st->cap_status;
-  const double tol = st->tol;
-  const int64_t max_iter = st->max_iter, hist_cap = st->hist_cap;
-  // column l of H-bar over the rows of blocks k-2 .. k+1
-  for (int e = tid; e < 4 * P * P; e += 64) {
-    const int l = e / (4 * P), r = e % (4 * P);
+__device__ void prev_rotations(BandShared<P>& sh) {
+  const int lane = threadIdx.x & 63;
+  // column l of H-bar over the rows of blocks k-2 .. k (zero, B_{k-1}, A_k)
+  for (int e = lane; e < 3 * P * P; e += 64) {
+    const int l = e / (3 * P), r = e % (3 * P);
     double v = 0.0;
     if (r >= P && r < 2 * P) v = (r - P >= l) ? sh.Bp[l][r - P] : 0.0;
-    if (r >= 2 * P && r < 3 * P) v = sh.Ak[r - 2 * P][l];
-    if (r >= 3 * P) v = (r - 3 * P <= l) ? sh.Bk[r - 3 * P][l] : 0.0;
+    if (r >= 2 * P) v = sh.Ak[r - 2 * P][l];
     sh.col[l][r] = v;
   }
   wave_sync();
-  // rotations of columns j-2p .. j-1 that lie in blocks k-2 (i >= l) and k-1
-  if (tid < P) {
-    const int l = tid;
-#pragma unroll 1
-    for (int b = 0; b < 2; ++b)
-#pragma unroll 1
-      for (int i = (b == 0 ? l : 0); i < P; ++i) {
-        const int base = b * P + i;
-        double x = sh.col[l][base], y[P];
+  // Rotations of blocks k-2 and k-1.  Rotation (b, i) mixes row bp+i of a
+  // column with the p rows below it, so lane l sweeps a window of p+1 rows
+  // down its column in registers: the top row is final once its rotations
+  // are applied and leaves the window, one untouched row enters at the
+  // bottom.  The rotations of block k-2 reach column l only from row l on.
+  // The next step's rotations and row are loaded ahead.  Row 3p, which
+  // enters the window after the last step, belongs to block k+1 and is not
+  // written yet: it is read but never used.
+  if (lane < P) {
+    const int l = lane;
+    double cw[P + 1];
 #pragma unroll
-        for (int t = 0; t < P; ++t) y[t] = sh.col[l][base + 1 + t];
+    for (int t = 0; t <= P; ++t) cw[t] = sh.col[l][t];
+    double rc[P], rs[P];
 #pragma unroll
-        for (int t = 0; t < P; ++t) rotate(sh.rot[b][i][t][0], sh.rot[b][i][t][1], x, y[t]);
-        sh.col[l][base] = x;
+    for (int t = 0; t < P; ++t) {
+      rc[t] = sh.rot[0][0][t][0];
+      rs[t] = sh.rot[0][0][t][1];
+    }
+    double nxt = sh.col[l][P + 1];
+    // unrolled so that a step's chain of p rotations overlaps the next
+    // step's, which needs only the first rotated row of this one
+#pragma unroll 4
+    for (int base = 0; base < 2 * P; ++base) {
+      const bool live = base >= P || base >= l;
+      double c[P], sn[P];
 #pragma unroll
-        for (int t = 0; t < P; ++t) sh.col[l][base + 1 + t] = y[t];
+      for (int t = 0; t < P; ++t) {
+        c[t] = rc[t];
+        sn[t] = rs[t];
       }
+      const double enter = nxt;
+      const int ahead = base + 1 < 2 * P ? base + 1 : base;
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        rc[t] = sh.rot[ahead / P][ahead % P][t][0];
+        rs[t] = sh.rot[ahead / P][ahead % P][t][1];
+      }
+      nxt = sh.col[l][ahead + 1 + P];
+      double x = cw[0], y[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) y[t] = cw[t + 1];
+#pragma unroll
+      for (int t = 0; t < P; ++t) rotate(c[t], sn[t], x, y[t]);
+      sh.col[l][base] = live ? x : cw[0];
+#pragma unroll
+      for (int t = 0; t < P; ++t) cw[t] = live ? y[t] : cw[t + 1];
+      cw[P] = enter;
+    }
+#pragma unroll
+    for (int t = 0; t < P; ++t) sh.col[l][2 * P + t] = cw[t];
   }
+}
+
+// Phase B: Givens QR of the p new columns of H-bar, S-hat window, residuals,
+// stopping test, coefficients of the search directions and of the X update.
+// Runs on the first wavefront after the rotations of the previous blocks.
+template <int P>
+__device__ void phase_b(const BandCtl ctl, DevState* __restrict__ st, double* __restrict__ hist, BandShared<P>& sh) {
+  const int tid = threadIdx.x;
+  const int64_t k = ctl.k;
+  const int64_t j0 = ctl.j0;
+  const int lcap = ctl.lcap, cap_status = ctl.cap_status;
+  const double tol = ctl.tol;
+  const int64_t max_iter = ctl.max_iter, hist_cap = ctl.hist_cap;
+  // rows 3p .. 4p-1 of column l (block k+1: B_k), then a row read ahead past
+  // the last column and never used; the rows above come from prev_rotations
+  for (int e = tid; e < P * (P + 1); e += 64) {
+    const int l = e / (P + 1), r = e % (P + 1);
+    sh.col[l][3 * P + r] = (r < P && r <= l) ? sh.Bk[r][l] : 0.0;
+  }
+  wave_sync();
+  // lane q: rows 2p .. 3p of column q, where the column's own rotations start
+  double cw[P + 1];
+#pragma unroll
+  for (int t = 0; t <= P; ++t) cw[t] = (tid < P) ? sh.col[tid][2 * P + t] : 0.0;
+  // lane q: rows i .. i+p of column q of S-hat (rows p and beyond start at 0)
+  double sw[P + 1];
+#pragma unroll
+  for (int t = 0; t <= P; ++t) sw[t] = (tid < P) ? sh.s2[tid][t] : 0.0;
   wave_sync();
 
   // 1 / ||b_q|| of this lane's column (0 for a zero right-hand side)
   const double binv = (tid < P && sh.beta[tid] > 0.0) ? 1.0 / sh.beta[tid] : 0.0;
+  const int q = tid < P ? tid : 0;
   int lstar = P, finished = 0, status = STATUS_RUNNING;
 #pragma unroll 1
   for (int i = 0; i < P; ++i) {
@@ -439,103 +652,115 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
     }
     const int64_t j = j0 + i + 1;
     const int piv = 2 * P + i;
-    {
-      // New rotations zero the p subdiagonal entries y_1..y_p of column j
-      // against its diagonal x_0.  Rotation t leaves
-      //     x_t = sqrt(x_0^2 + y_1^2 + ... + y_t^2)
-      // on the diagonal (x_0 itself while y_1..y_t are all zero, the identity
-      // rotations of givens()), and is c_t = x_{t-1} / x_t, s_t = y_t / x_t.
-      // Lane t-1 forms x_t from a prefix sum of squares over the lanes,
-      // scaled by a power of two near the column's largest magnitude, so the
-      // p rotations come out at once instead of through p dependent hypot
-      // calls.
-      const double x0 = sh.col[i][piv];
-      const double y = (tid < P) ? sh.col[i][piv + 1 + tid] : 0.0;
-      double m = fabs(y);
+    // everything this column reads from the other lanes, in one batch: the
+    // pivot column i (rows piv .. piv+p) and its rows q, p+q, 2p+q for R;
+    // then the row entering this lane's window
+    const double x0 = sh.col[i][piv];
+    const double y = (tid < P) ? sh.col[i][piv + 1 + tid] : 0.0;
+    const double ra = sh.col[i][q], rb = sh.col[i][P + q], rcv = sh.col[i][2 * P + q];
+    const double enter = sh.col[q][piv + 1 + P];
+    // New rotations zero the p subdiagonal entries y_1..y_p of column j
+    // against its diagonal x_0.  Rotation t leaves
+    //     x_t = sqrt(x_0^2 + y_1^2 + ... + y_t^2)
+    // on the diagonal (x_0 itself while y_1..y_t are all zero, the identity
+    // rotations of givens()), and is c_t = x_{t-1} / x_t, s_t = y_t / x_t.
+    // Lane t-1 forms x_t from a prefix sum of squares over the lanes,
+    // scaled by a power of two near the column's largest magnitude, so the
+    // p rotations come out at once instead of through p dependent hypot
+    // calls.
+    double m = row_max(fabs(y));
+    m = fmax(m, fabs(x0));
+    // power-of-two scale: exact, and keeps the squares in range
+    int ex = 0;
+    if (m > 0.0 && isfinite(m)) (void)frexp(m, &ex);
+    const double inv = ldexp(1.0, -ex), scl = ldexp(1.0, ex);
+    double ps = (y * inv) * (y * inv);
+    int nz = (y != 0.0) ? 1 : 0;
 #pragma unroll
-      for (int o = 1; o < 16; o <<= 1) m = fmax(m, __shfl_xor(m, o, 16));
-      m = fmax(m, fabs(x0));
-      // power-of-two scale: exact, and keeps the squares in range
-      int ex = 0;
-      if (m > 0.0 && isfinite(m)) (void)frexp(m, &ex);
-      const double inv = ldexp(1.0, -ex), scl = ldexp(1.0, ex);
-      double ps = (y * inv) * (y * inv);
-      int nz = (y != 0.0) ? 1 : 0;
-#pragma unroll
-      for (int o = 1; o < P; o <<= 1) {
-        const double a = __shfl_up(ps, o, 64);
-        const int b = __shfl_up(nz, o, 64);
-        if (tid >= o) {
-          ps += a;
-          nz |= b;
-        }
-      }
-      const double xs = x0 * inv;
-      const double xt = nz ? scl * sqrt(xs * xs + ps) : x0;
-      double xprev = __shfl_up(xt, 1, 64);
-      if (tid == 0) xprev = x0;
-      if (tid < P) {
-        const bool ident = (y == 0.0);
-        const double rinv = 1.0 / xt;
-        sh.nrot[i][tid][0] = ident ? 1.0 : xprev * rinv;
-        sh.nrot[i][tid][1] = ident ? 0.0 : y * rinv;
-      }
-      if (tid == P - 1) {
-        sh.col[i][piv] = xt;
-        sh.piv = xt;
-      }
+    for (int o = 1; o < P; o <<= 1) {  // inclusive scan; lanes below o add 0
+      ps += row_shr(ps, o);
+      nz |= row_shr(nz, o);
     }
-    wave_sync();
-    if (!(sh.piv != 0.0)) {
+    const double xs = x0 * inv;
+    const double xt = nz ? scl * sqrt(xs * xs + ps) : x0;
+    double xprev = row_shr(xt, 1);
+    if (tid == 0) xprev = x0;
+    if (tid < P) {
+      const bool ident = (y == 0.0);
+      const double rinv = 1.0 / xt;
+      sh.nrot[i][tid][0] = ident ? 1.0 : xprev * rinv;
+      sh.nrot[i][tid][1] = ident ? 0.0 : y * rinv;
+    }
+    const double pivot = lane_value(xt, P - 1);  // the new diagonal entry
+    if (!(pivot != 0.0)) {
       if (tid == 0) {
-        halt_with(st, isfinite(sh.piv) ? BMR_SINGULAR_R : BMR_NONFINITE, REASON_ERROR);
+        halt_with(st, isfinite(pivot) ? BMR_SINGULAR_R : BMR_NONFINITE, REASON_ERROR);
         st->j = j - 1;
       }
       return;
     }
+    wave_sync();
     double ratio = 0.0;
     if (tid < P) {
-      const int q = tid;
-      // column j of R: rows of blocks k-2, k-1 and k (lane q writes row q of each)
-      sh.Ra[q][i] = (q >= i) ? sh.col[i][q] : 0.0;
-      sh.Rb[q][i] = sh.col[i][P + q];
-      sh.Rc[q][i] = (q <= i) ? sh.col[i][2 * P + q] : 0.0;
-      if (q > i) {  // later columns of the block receive the rotations of column i
-        double x = sh.col[q][piv], y[P];
-#pragma unroll
-        for (int t = 0; t < P; ++t) y[t] = sh.col[q][piv + 1 + t];
-#pragma unroll
-        for (int t = 0; t < P; ++t) rotate(sh.nrot[i][t][0], sh.nrot[i][t][1], x, y[t]);
-        sh.col[q][piv] = x;
-#pragma unroll
-        for (int t = 0; t < P; ++t) sh.col[q][piv + 1 + t] = y[t];
-      }
-      // S-hat rows i .. i+p of column q
-      double x = sh.s2[q][i], y[P];
-#pragma unroll
-      for (int t = 0; t < P; ++t) y[t] = sh.s2[q][i + 1 + t];
-#pragma unroll
-      for (int t = 0; t < P; ++t)
-        if (sh.nrot[i][t][1] != 0.0) rotate(sh.nrot[i][t][0], sh.nrot[i][t][1], x, y[t]);
-      sh.s2[q][i] = x;
-      // recurrence residual rho_j^{(q)} = ||S-hat(j+1:j+p, q)|| (eq. (3.5))
-      double ss = 0.0;
+      double c[P], sn[P];
 #pragma unroll
       for (int t = 0; t < P; ++t) {
-        sh.s2[q][i + 1 + t] = y[t];
-        ss += y[t] * y[t];
+        c[t] = sh.nrot[i][t][0];
+        sn[t] = sh.nrot[i][t][1];
       }
+      // column j of R: rows of blocks k-2, k-1 and k (lane q writes row q of each)
+      sh.Ra[q][i] = (q >= i) ? ra : 0.0;
+      sh.Rb[q][i] = rb;
+      sh.Rc[q][i] = (q < i) ? rcv : (q == i) ? pivot : 0.0;
+      if (q > i) {  // later columns of the block receive the rotations of column i
+        double x = cw[0], yy[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) yy[t] = cw[t + 1];
+#pragma unroll
+        for (int t = 0; t < P; ++t) rotate(c[t], sn[t], x, yy[t]);
+        sh.col[q][piv] = x;
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+          sh.col[q][piv + 1 + t] = yy[t];
+          cw[t] = yy[t];
+        }
+        cw[P] = enter;
+      }
+      // S-hat rows i .. i+p of column q; identity rotations are skipped
+      double x = sw[0], yy[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) yy[t] = sw[t + 1];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        double a = x, b = yy[t];
+        rotate(c[t], sn[t], a, b);
+        const bool id = sn[t] == 0.0;
+        x = id ? x : a;
+        yy[t] = id ? yy[t] : b;
+      }
+      // recurrence residual rho_j^{(q)} = ||S-hat(j+1:j+p, q)|| (eq. (3.5)),
+      // the squares summed pairwise
+      double sq[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        sw[t] = yy[t];
+        sq[t] = yy[t] * yy[t];
+      }
+      sw[P] = 0.0;
+#pragma unroll
+      for (int w = 1; w < P; w <<= 1)
+#pragma unroll
+        for (int t = 0; t + w < P; t += 2 * w) sq[t] += sq[t + w];
+      const double ss = sq[0];
       ratio = binv > 0.0 ? sqrt(ss) * binv : 0.0;
       sh.Zk[i][q] = x;
       st->rho[q] = ratio;
       if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
     }
     // stopping test over the columns (lanes 0..p-1 of the first 16): the
-    // largest ratio, with a non-finite ratio counted as +inf
-    double worst = isfinite(ratio) ? ratio : INFINITY;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) worst = fmax(worst, __shfl_xor(worst, o, 16));
-    worst = __shfl(worst, 0, 64);  // every lane takes lane 0's decision
+    // largest ratio, with a non-finite ratio counted as +inf; every lane
+    // takes lane 0's decision
+    const double worst = lane_value(row_max(isfinite(ratio) ? ratio : INFINITY), 0);
     const int f = (worst == INFINITY) ? 2 : (worst < tol) ? 1 : (j >= max_iter) ? 3 : 0;
     if (f == 2) {
       if (tid == 0) {
@@ -551,6 +776,11 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
       break;
     }
     wave_sync();
+  }
+  // S-hat rows p .. 2p-1, carried to the next block
+  if (!finished && tid < P) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) sh.s2[tid][P + t] = sw[t];
   }
   wave_sync();
   search_coefficients<P>(st, sh, k, lstar, finished);
@@ -585,43 +815,54 @@ __device__ void phase_b(DevState* __restrict__ st, double* __restrict__ hist, Ba
 
 // mode 0: phase A then phase B.  mode 1: the host has supplied B_k (column-
 // wise QR) and already formed V_{k+1}; run phase B with pass 2 told to keep
-// V_{k+1} as it is.
+// V_{k+1} as it is.  nb: bench vectors (the state's nb).
+//
+// Two wavefronts: the first loads the inputs and runs phase A; the second
+// applies the rotations of the previous blocks meanwhile (they need only
+// B_{k-1} and A_k).  The first then runs phase B alone.  Both wavefronts
+// reach both barriers on every path that gets past the halt test.
 template <int P>
-__global__ __launch_bounds__(64) void k_band(int mode, const double* __restrict__ red, double* __restrict__ hist,
-                                            DevState* __restrict__ st) {
+__global__ __launch_bounds__(128) void k_band(int mode, int nb, const double* __restrict__ red,
+                                             double* __restrict__ hist, DevState* __restrict__ st) {
   __shared__ BandShared<P> sh;
-  const int tid = threadIdx.x;
-  if (tid == 0) sh.flag = st->halt;
-  wave_sync();
-  if (sh.flag) {
-    if (tid == 0) st->k2 = 0;
+  const bool first = threadIdx.x < 64;
+  BandCtl ctl;
+  BandLoads<P> L;
+  if (first) load_band<P>(mode, nb, red, st, ctl, L);
+  else ctl.halt = st->halt;
+  if (ctl.halt) {  // the same in both wavefronts: nothing writes it meanwhile
+    if (threadIdx.x == 0) st->k2 = 0;
     return;
   }
-  wave_sync();
-  load_band_inputs<P>(st, sh);
-  if (mode == 0) {
-    if (!phase_a<P>(red, st, sh)) {
-      if (tid == 0) {
+  if (first) {
+    store_band_inputs<P>(mode, nb, ctl, L, sh);
+    if (mode == 0) phase_a_ak<P>(sh);
+  }
+  wg_lds_sync();  // B_{k-1}, A_k and the rotations are in LDS
+  bool ok = true;
+  if (first) {
+    if (mode == 0) {
+      ok = phase_a<P>(nb, ctl.taken, ctl.tau_fb, st, sh);
+      if (!ok && threadIdx.x == 0) {
         for (int e = 0; e < P * P; ++e) st->Ak[(e / P) * MAXP + (e % P)] = sh.Ak[e / P][e % P];
         for (int c = 0; c < P; ++c) st->araw[c] = sh.araw[c];
         st->reason = REASON_EXPLICIT_QR;
         st->halt = 1;
         st->k2 = 0;
       }
-      return;
+    } else {
+      for (int e = threadIdx.x; e < P * P; e += 64) {
+        const int r = e / P, c = e % P;
+        st->P2A[r * MAXP + c] = 0.0;
+        st->P2B[r * MAXP + c] = (r == c) ? 1.0 : 0.0;
+      }
+      for (int e = threadIdx.x; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
     }
   } else {
-    for (int e = tid; e < P * P; e += 64) {
-      const int r = e / P, c = e % P;
-      sh.Ak[r][c] = st->Ak[r * MAXP + c];
-      sh.Bk[r][c] = st->Bk[r * MAXP + c];
-      st->P2A[r * MAXP + c] = 0.0;
-      st->P2B[r * MAXP + c] = (r == c) ? 1.0 : 0.0;
-    }
-    for (int e = tid; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
-    wave_sync();
+    prev_rotations<P>(sh);
   }
-  phase_b<P>(st, hist, sh);
+  wg_lds_sync();  // rows 0 .. 3p-1 of the columns rotated, B_k in LDS
+  if (first && ok) phase_b<P>(ctl, st, hist, sh);
 }
 
 }  // namespace
@@ -632,8 +873,9 @@ hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, D
   return hipGetLastError();
 }
 
-hipError_t launch_band(int p, int mode, const double* red, double* hist, DevState* st, hipStream_t s) {
-#define LB(P) hipLaunchKernelGGL(k_band<P>, dim3(1), dim3(64), 0, s, mode, red, hist, st)
+hipError_t launch_band(int p, int mode, int nb, const double* red, double* hist, DevState* st, hipStream_t s) {
+  if (nb < 0 || nb > MAXB) return hipErrorInvalidValue;
+#define LB(P) hipLaunchKernelGGL(k_band<P>, dim3(1), dim3(128), 0, s, mode, nb, red, hist, st)
   switch (p) {
     case 1: LB(1); break;
     case 2: LB(2); break;

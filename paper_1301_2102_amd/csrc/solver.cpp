@@ -392,7 +392,7 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
       if (prof) HIP_TRY(hipEventRecord(pev[slot][1], r.s));
       HIP_TRY(launch_reduce(r.part, r.n_wg, n_entries(r.p, r.nb), r.red, r.st, 1, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][2], r.s));
-      HIP_TRY(launch_band(r.p, 0, r.red, r.hist, r.st, r.s));
+      HIP_TRY(launch_band(r.p, 0, r.nb, r.red, r.hist, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][3], r.s));
       HIP_TRY(launch_pass2<T>(r.p, r.V, r.slot, r.bench, r.n, r.st, r.s));
       if (kq % grp == 0) TRY(flush(kq));
@@ -444,7 +444,7 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     hs->halt = 0;
     hs->reason = REASON_NONE;
     HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
-    HIP_TRY(launch_band(r.p, 1, r.red, r.hist, r.st, r.s));
+    HIP_TRY(launch_band(r.p, 1, r.nb, r.red, r.hist, r.st, r.s));
     HIP_TRY(launch_pass2<T>(r.p, r.V, r.slot, r.bench, r.n, r.st, r.s));
     TRY(flush(k));
     last_explicit = k;
