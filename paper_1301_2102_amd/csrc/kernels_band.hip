@@ -157,8 +157,6 @@ struct BandShared {
   double nrot[P][P][2];    // rotations of block k
   double col[P][4 * P + 1];  // column l of H-bar, rows of blocks k-2 .. k+1
   double s2[P][2 * P + 1];   // column q of the S-hat window (p live + p new rows)
-  double piv;
-  int flag;
 };
 
 // Scalars of the state the band kernel reads, loaded once at its start.
@@ -276,24 +274,32 @@ __device__ bool phase_a(int nb, int taken, double tau_fb, DevState* __restrict__
   }
   wave_sync();
   // right-looking Cholesky T2 = B_k^T B_k; each entry sees its subtractions
-  // in the same order as the row-oriented recurrence
+  // in the same order as the row-oriented recurrence.  Every lane forms the
+  // pivot test and the entries of row l of B_k it needs itself, so a column
+  // costs one exchange through LDS.
+  constexpr int N = (P * P + 63) / 64;
 #pragma unroll 1
   for (int l = 0; l < P; ++l) {
-    if (tid == 0) {
-      const double d = sh.T2[l][l];
-      const double thr = tau_fb * sh.araw[l];
-      const bool ok = (d > 0.0) && isfinite(d) && (sqrt(d) >= thr);
-      sh.flag = ok;
-      sh.piv = ok ? sqrt(d) : 0.0;
+    const double d = sh.T2[l][l];
+    const double thr = tau_fb * sh.araw[l];
+    double tr[N], tc[N];
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      const int e = tid + 64 * x, r = (e / P) % P, c = e % P;
+      tr[x] = sh.T2[l][r];
+      tc[x] = sh.T2[l][c];
     }
-    wave_sync();
-    if (!sh.flag) return false;
-    if (tid == l) sh.Bk[l][l] = sh.piv;
-    if (tid > l && tid < P) sh.Bk[l][tid] = sh.T2[l][tid] / sh.piv;
-    wave_sync();
-    for (int e = tid; e < P * P; e += 64) {
-      const int r = e / P, c = e % P;
-      if (r > l && c > l) sh.T2[r][c] -= sh.Bk[l][r] * sh.Bk[l][c];
+    const bool ok = (d > 0.0) && isfinite(d) && (sqrt(d) >= thr);
+    if (!ok) return false;
+    const double piv = sqrt(d), inv = 1.0 / piv;
+#pragma unroll
+    for (int x = 0; x < N; ++x) {
+      const int e = tid + 64 * x, r = e / P, c = e % P;
+      if (e < P * P) {
+        const double bc = tc[x] * inv;  // B_k(l, c)
+        if (r == l && c >= l) sh.Bk[l][c] = (c == l) ? piv : bc;
+        if (r > l && c > l) sh.T2[r][c] -= (tr[x] * inv) * bc;
+      }
     }
     wave_sync();
   }
@@ -628,19 +634,20 @@ __device__ void phase_b(const BandCtl ctl, DevState* __restrict__ st, double* __
     sh.col[l][3 * P + r] = (r < P && r <= l) ? sh.Bk[r][l] : 0.0;
   }
   wave_sync();
-  // lane q: rows 2p .. 3p of column q, where the column's own rotations start
-  double cw[P + 1];
+  // Each column of the block has two windows of p+1 rows that the column's
+  // rotations sweep down: one of H-bar, held by lane q of the first row of
+  // 16 lanes (rows 2p+i .. 3p+i at column i), and one of S-hat, held by lane
+  // 16+q of the second row (rows i .. i+p; rows p and beyond start at 0).
+  // Both rows apply the same rotations in the same instructions.
+  const bool hlane = tid < P, slane = tid >= 16 && tid < 16 + P;
+  const int q = hlane ? tid : slane ? tid - 16 : 0;
+  double win[P + 1];
 #pragma unroll
-  for (int t = 0; t <= P; ++t) cw[t] = (tid < P) ? sh.col[tid][2 * P + t] : 0.0;
-  // lane q: rows i .. i+p of column q of S-hat (rows p and beyond start at 0)
-  double sw[P + 1];
-#pragma unroll
-  for (int t = 0; t <= P; ++t) sw[t] = (tid < P) ? sh.s2[tid][t] : 0.0;
+  for (int t = 0; t <= P; ++t) win[t] = hlane ? sh.col[q][2 * P + t] : slane ? sh.s2[q][t] : 0.0;
   wave_sync();
 
-  // 1 / ||b_q|| of this lane's column (0 for a zero right-hand side)
-  const double binv = (tid < P && sh.beta[tid] > 0.0) ? 1.0 / sh.beta[tid] : 0.0;
-  const int q = tid < P ? tid : 0;
+  // 1 / ||b_q|| of the S-hat lane's column (0 for a zero right-hand side)
+  const double binv = (slane && sh.beta[q] > 0.0) ? 1.0 / sh.beta[q] : 0.0;
   int lstar = P, finished = 0, status = STATUS_RUNNING;
 #pragma unroll 1
   for (int i = 0; i < P; ++i) {
@@ -658,7 +665,7 @@ __device__ void phase_b(const BandCtl ctl, DevState* __restrict__ st, double* __
     const double x0 = sh.col[i][piv];
     const double y = (tid < P) ? sh.col[i][piv + 1 + tid] : 0.0;
     const double ra = sh.col[i][q], rb = sh.col[i][P + q], rcv = sh.col[i][2 * P + q];
-    const double enter = sh.col[q][piv + 1 + P];
+    const double enter = hlane ? sh.col[q][piv + 1 + P] : 0.0;
     // New rotations zero the p subdiagonal entries y_1..y_p of column j
     // against its diagonal x_0.  Rotation t leaves
     //     x_t = sqrt(x_0^2 + y_1^2 + ... + y_t^2)
@@ -700,67 +707,53 @@ __device__ void phase_b(const BandCtl ctl, DevState* __restrict__ st, double* __
       return;
     }
     wave_sync();
+    if (hlane) {  // column j of R: rows of blocks k-2, k-1 and k (lane q writes row q of each)
+      sh.Ra[q][i] = (q >= i) ? ra : 0.0;
+      sh.Rb[q][i] = rb;
+      sh.Rc[q][i] = (q < i) ? rcv : (q == i) ? pivot : 0.0;
+    }
     double ratio = 0.0;
-    if (tid < P) {
+    // the rotations of column i reach the later columns of the block and
+    // every column of S-hat
+    if ((hlane && q > i) || slane) {
       double c[P], sn[P];
 #pragma unroll
       for (int t = 0; t < P; ++t) {
         c[t] = sh.nrot[i][t][0];
         sn[t] = sh.nrot[i][t][1];
       }
-      // column j of R: rows of blocks k-2, k-1 and k (lane q writes row q of each)
-      sh.Ra[q][i] = (q >= i) ? ra : 0.0;
-      sh.Rb[q][i] = rb;
-      sh.Rc[q][i] = (q < i) ? rcv : (q == i) ? pivot : 0.0;
-      if (q > i) {  // later columns of the block receive the rotations of column i
-        double x = cw[0], yy[P];
+      double x = win[0], yy[P];
 #pragma unroll
-        for (int t = 0; t < P; ++t) yy[t] = cw[t + 1];
+      for (int t = 0; t < P; ++t) yy[t] = win[t + 1];
 #pragma unroll
-        for (int t = 0; t < P; ++t) rotate(c[t], sn[t], x, yy[t]);
+      for (int t = 0; t < P; ++t) rotate(c[t], sn[t], x, yy[t]);
+#pragma unroll
+      for (int t = 0; t < P; ++t) win[t] = yy[t];
+      win[P] = enter;
+      if (hlane) {
         sh.col[q][piv] = x;
 #pragma unroll
-        for (int t = 0; t < P; ++t) {
-          sh.col[q][piv + 1 + t] = yy[t];
-          cw[t] = yy[t];
-        }
-        cw[P] = enter;
+        for (int t = 0; t < P; ++t) sh.col[q][piv + 1 + t] = yy[t];
+      } else {
+        // recurrence residual rho_j^{(q)} = ||S-hat(j+1:j+p, q)|| (eq. (3.5)),
+        // the squares summed pairwise
+        double sq[P];
+#pragma unroll
+        for (int t = 0; t < P; ++t) sq[t] = yy[t] * yy[t];
+#pragma unroll
+        for (int w = 1; w < P; w <<= 1)
+#pragma unroll
+          for (int t = 0; t + w < P; t += 2 * w) sq[t] += sq[t + w];
+        ratio = binv > 0.0 ? sqrt(sq[0]) * binv : 0.0;
+        sh.Zk[i][q] = x;
+        st->rho[q] = ratio;
+        if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
       }
-      // S-hat rows i .. i+p of column q; identity rotations are skipped
-      double x = sw[0], yy[P];
-#pragma unroll
-      for (int t = 0; t < P; ++t) yy[t] = sw[t + 1];
-#pragma unroll
-      for (int t = 0; t < P; ++t) {
-        double a = x, b = yy[t];
-        rotate(c[t], sn[t], a, b);
-        const bool id = sn[t] == 0.0;
-        x = id ? x : a;
-        yy[t] = id ? yy[t] : b;
-      }
-      // recurrence residual rho_j^{(q)} = ||S-hat(j+1:j+p, q)|| (eq. (3.5)),
-      // the squares summed pairwise
-      double sq[P];
-#pragma unroll
-      for (int t = 0; t < P; ++t) {
-        sw[t] = yy[t];
-        sq[t] = yy[t] * yy[t];
-      }
-      sw[P] = 0.0;
-#pragma unroll
-      for (int w = 1; w < P; w <<= 1)
-#pragma unroll
-        for (int t = 0; t + w < P; t += 2 * w) sq[t] += sq[t + w];
-      const double ss = sq[0];
-      ratio = binv > 0.0 ? sqrt(ss) * binv : 0.0;
-      sh.Zk[i][q] = x;
-      st->rho[q] = ratio;
-      if (j <= hist_cap) hist[(j - 1) * P + q] = ratio;
     }
-    // stopping test over the columns (lanes 0..p-1 of the first 16): the
-    // largest ratio, with a non-finite ratio counted as +inf; every lane
-    // takes lane 0's decision
-    const double worst = lane_value(row_max(isfinite(ratio) ? ratio : INFINITY), 0);
+    // stopping test over the columns (the S-hat lanes, in the second row):
+    // the largest ratio, with a non-finite ratio counted as +inf; every lane
+    // takes lane 16's decision
+    const double worst = lane_value(row_max(isfinite(ratio) ? ratio : INFINITY), 16);
     const int f = (worst == INFINITY) ? 2 : (worst < tol) ? 1 : (j >= max_iter) ? 3 : 0;
     if (f == 2) {
       if (tid == 0) {
@@ -778,9 +771,9 @@ __device__ void phase_b(const BandCtl ctl, DevState* __restrict__ st, double* __
     wave_sync();
   }
   // S-hat rows p .. 2p-1, carried to the next block
-  if (!finished && tid < P) {
+  if (!finished && slane) {
 #pragma unroll
-    for (int t = 0; t < P; ++t) sh.s2[tid][P + t] = sw[t];
+    for (int t = 0; t < P; ++t) sh.s2[q][P + t] = win[t];
   }
   wave_sync();
   search_coefficients<P>(st, sh, k, lstar, finished);
