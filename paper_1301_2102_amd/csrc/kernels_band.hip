@@ -33,21 +33,28 @@
 namespace bmr {
 namespace {
 
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part, int n_wg, double* __restrict__ red,
-                                                DevState* __restrict__ st, int check_halt) {
+// One wavefront per entry: each lane keeps four partial sums, with up to
+// sixteen loads in flight, then the wavefront adds its lanes by shuffles.
+// The order of the additions is fixed, so the result is reproducible.
+__global__ __launch_bounds__(64) void k_reduce(const double* __restrict__ part, int n_wg, double* __restrict__ red,
+                                               DevState* __restrict__ st, int check_halt) {
   if (check_halt && st->halt) return;
   const int e = blockIdx.x;
   const double* src = part + (size_t)e * n_wg;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n_wg; i += 256) s += src[i];
-  __shared__ double sh[256];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = threadIdx.x;
+#pragma unroll 4
+  for (; i + 192 < n_wg; i += 256) {
+    s0 += src[i];
+    s1 += src[i + 64];
+    s2 += src[i + 128];
+    s3 += src[i + 192];
   }
-  if (threadIdx.x == 0) red[e] = sh[0];
+  for (; i < n_wg; i += 64) s0 += src[i];
+  double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) red[e] = s;
 }
 
 // The band kernel runs as a single wavefront (64 lanes).  Its barriers only
@@ -412,38 +419,44 @@ __device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh
   constexpr int S = group_len(P);
   const int tid = threadIdx.x;
   const int t = (int)((k - 1) % S);
-  // C = R_c^{-1} (upper triangular) on the leading l* columns: lane q forms row q
+  // C = R_c^{-1} (upper triangular) on the leading l* columns: lane q forms
+  // row q in registers (entries left of the diagonal are 0 and add nothing)
   if (tid < P) {
     const int q = tid;
-#pragma unroll 1
+    double crow[P];
+#pragma unroll
     for (int i = 0; i < P; ++i) {
-      double c = 0.0;
-      if (i < lstar && q <= i) {
-        double a = (q == i) ? 1.0 : 0.0;
-        for (int r = q; r < i; ++r) a -= sh.C[q][r] * sh.Rc[r][i];
-        c = a / sh.Rc[i][i];
-      }
-      sh.C[q][i] = c;
+      double a = (q == i) ? 1.0 : 0.0;
+#pragma unroll
+      for (int r = 0; r < i; ++r) a = fma(-crow[r], sh.Rc[r][i], a);
+      crow[i] = (i < lstar && q <= i) ? a / sh.Rc[i][i] : 0.0;
+      sh.C[q][i] = crow[i];
     }
   }
   wave_sync();
-  for (int e = tid; e < P * P; e += 64) {
-    const int q = e / P, i = e % P;
-    double d = 0.0, f = 0.0;
-    if (i < lstar) {
-      for (int r = 0; r <= i; ++r) {
-        d -= sh.Rb[q][r] * sh.C[r][i];
-        f -= sh.Ra[q][r] * sh.C[r][i];
+  constexpr int NQ = (P * P + 63) / 64;
+#pragma unroll
+  for (int x = 0; x < NQ; ++x) {
+    const int e = tid + 64 * x;
+    if (e < P * P) {
+      const int q = e / P, i = e % P;
+      double d = 0.0, f = 0.0;
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        const bool use = i < lstar && r <= i;
+        const double cri = sh.C[r][i];
+        d = use ? fma(-sh.Rb[q][r], cri, d) : d;
+        f = use ? fma(-sh.Ra[q][r], cri, f) : f;
       }
+      const double z = (q < lstar) ? sh.Zk[q][i] : 0.0;
+      sh.D[q][i] = d;
+      sh.E[q][i] = f;
+      sh.Zk[q][i] = z;
+      st->gC[t][q * MAXP + i] = sh.C[q][i];
+      st->gD[t][q * MAXP + i] = d;
+      st->gE[t][q * MAXP + i] = f;
+      st->gZ[t][q * MAXP + i] = z;
     }
-    const double z = (q < lstar) ? sh.Zk[q][i] : 0.0;
-    sh.D[q][i] = d;
-    sh.E[q][i] = f;
-    sh.Zk[q][i] = z;
-    st->gC[t][q * MAXP + i] = sh.C[q][i];
-    st->gD[t][q * MAXP + i] = d;
-    st->gE[t][q * MAXP + i] = f;
-    st->gZ[t][q * MAXP + i] = z;
   }
   wave_sync();
   if (!finishing && t != S - 1) return;
@@ -862,7 +875,7 @@ __global__ __launch_bounds__(128) void k_band(int mode, int nb, const double* __
 
 hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, DevState* st, int check_halt,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(n_ent), dim3(256), 0, s, part, n_wg, red, st, check_halt);
+  hipLaunchKernelGGL(k_reduce, dim3(n_ent), dim3(64), 0, s, part, n_wg, red, st, check_halt);
   return hipGetLastError();
 }
 

@@ -347,7 +347,7 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     }
   } evg{ev};
   int batch = o.poll_every;
-  if (batch <= 0) batch = ((double)n * p < 2e6) ? 32 : 8;
+  if (batch <= 0) batch = ((double)n * p < 2e6) ? 32 : 16;
   const bool prof = o.prof;
   if (prof) batch = 1;
   hipEvent_t pev[2][5];
