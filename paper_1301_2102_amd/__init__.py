@@ -23,8 +23,9 @@ MAX_BENCH = 4
 
 def group_len(p: int) -> int:
     """Blocks per group of search directions (the library applies eq. (4.2)
-    once per group): min(16, max(2, 1024 // p^2)), as in the library."""
-    return min(16, max(2, 1024 // (p * p)))
+    once per group): min(32, 2048 // p^2) for p <= 8, max(2, 1024 // p^2)
+    above, as in the library."""
+    return min(32, 2048 // (p * p)) if p <= 8 else max(2, 1024 // (p * p))
 
 CONVERGED = 0
 MAX_ITER = 1

@@ -17,19 +17,17 @@ constexpr int STATUS_RUNNING = 100;
 // The search directions and the iterate (eqs. (4.1)-(4.2)) are applied in
 // groups of s = group_len(p) blocks: pass 2 of the group's last block adds
 // the group's contributions to X from the group's Lanczos blocks and the two
-// search-direction blocks before the group.  s is capped so that the
-// 3 (s + 2) p x p coefficient blocks of a group fit in LDS.  V_k lives in
-// slot k mod ring_len(p) of the V ring.  The ring holds two groups and two
-// more blocks, so that a group's flush may run in row chunks during the
-// next group (its first slot is rewritten by pass 2 of block g + 2s + 2).
-constexpr int MAXS = 16;
+// search-direction blocks before the group.  The flush moves s + 6 blocks
+// per s block iterations, so longer groups move fewer bytes; s is capped so
+// that the 3 (s + 2) p x p coefficient blocks of a group fit in the LDS of
+// the flush and of the band kernel: 2048 / p^2 up to 32 blocks for p <= 8
+// (where the flush runs one wavefront per SIMD), 1024 / p^2 above.  V_k
+// lives in slot k mod ring_len(p) of the V ring.
+constexpr int MAXS = 32;
 __host__ __device__ constexpr int group_len(int p) {
-  return 1024 / (p * p) > MAXS ? MAXS : (1024 / (p * p) < 2 ? 2 : 1024 / (p * p));
+  return p <= 8 ? (2048 / (p * p) > MAXS ? MAXS : 2048 / (p * p)) : (1024 / (p * p) < 2 ? 2 : 1024 / (p * p));
 }
-__host__ __device__ constexpr int ring_len(int p) { return 2 * group_len(p) + 2; }
-// Flush coefficients of the group that block k belongs to sit in buffer
-// flush_buf(k, p) of DevState::Y (groups alternate between two buffers).
-__host__ __device__ constexpr int flush_buf(int64_t k, int p) { return (int)(((k - 1) / group_len(p)) % 2); }
+__host__ __device__ constexpr int ring_len(int p) { return group_len(p) + 2; }
 
 // Why the device loop stopped (DevState::reason).
 enum : int {
@@ -102,11 +100,10 @@ struct DevState {
   //     out_o = [X if o = 0] + sum_{t<m} V_{g+1+t} Y[o][t] + M_g Y[o][MAXS] + M_{g-1} Y[o][MAXS+1],
   // o = 0: X, o = 1: M_{g+m-1}, o = 2: M_{g+m} (the two blocks the next group
   // starts from; not needed when the iteration stops at g + m).
-  // Two buffers, by the parity of the group (flush_buf).
-  double Y[2][3][MAXS + 2][MAXP * MAXP];
-  int64_t flush_block[2];  // g + m of the last group whose coefficients are in the buffer
-  int flush_len[2];        // m
-  int flush_keep[2];       // != 0: the flush also writes M_{g+m-1} and M_{g+m}
+  double Y[3][MAXS + 2][MAXP * MAXP];
+  int64_t flush_block;  // g + m of the last group whose coefficients are in Y
+  int flush_len;        // m
+  int flush_keep;       // != 0: the flush also writes M_{g+m-1} and M_{g+m}
 };
 
 // Workspace carve-up (offsets into the caller's workspace).  The blocks V, M
@@ -142,12 +139,11 @@ hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, D
 hipError_t launch_band(int p, int mode, int nb, const double* red, double* hist, DevState* st, hipStream_t s);
 template <typename T>
 hipError_t launch_pass2(int p, T* Vbase, size_t slot_elems, T* bench, int64_t n, DevState* st, hipStream_t s);
-// The group's search directions into X (and the next group's two M blocks)
-// on rows row0 .. row1-1; does nothing unless the band kernel recorded a
-// group ending at block k.
+// The group's search directions into X (and the next group's two M blocks);
+// does nothing unless the band kernel recorded a group ending at block k.
 template <typename T>
-hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot_elems, T* X, int64_t row0, int64_t row1,
-                        int64_t k, const DevState* st, hipStream_t s);
+hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot_elems, T* X, int64_t n, int64_t k,
+                        const DevState* st, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s);
 template <typename T>

@@ -504,7 +504,6 @@ __device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh
   auto cE = [&](int u, int r, int c) { return sh.gs[2][u][r][c]; };
   auto cZ = [&](int u, int r, int c) { return sh.gs[3][u][r][c]; };
   const int m = t + 1;
-  const int fb = flush_buf(k, P);
   // the three outputs' recurrences run side by side (one element of each
   // per lane and step), which hides the latency of their dependent chains
   constexpr int NE = 3 * P * P, IT = (NE + 63) / 64;
@@ -532,7 +531,7 @@ __device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh
         const int o = e / (P * P), q = (e / P) % P, c = e % P;
         double y = 0.0;
         for (int r = q; r < P; ++r) y += cC(u, q, r) * sh.Tr[o][s0][r][c];
-        st->Y[fb][o][u][q * MAXP + c] = y;
+        st->Y[o][u][q * MAXP + c] = y;
       }
     }
     wave_sync();
@@ -549,15 +548,15 @@ __device__ void search_coefficients(DevState* __restrict__ st, BandShared<P>& sh
       }
       if (m >= 2)
         for (int i = 0; i < P; ++i) yb += cE(1, q, i) * sh.Tr[o][1][i][c];
-      st->Y[fb][o][MAXS][q * MAXP + c] = yb;
-      st->Y[fb][o][MAXS + 1][q * MAXP + c] = ya;
+      st->Y[o][MAXS][q * MAXP + c] = yb;
+      st->Y[o][MAXS + 1][q * MAXP + c] = ya;
     }
   }
   wave_sync();
   if (tid == 0) {
-    st->flush_len[fb] = m;
-    st->flush_keep[fb] = finishing ? 0 : 1;
-    st->flush_block[fb] = k;
+    st->flush_len = m;
+    st->flush_keep = finishing ? 0 : 1;
+    st->flush_block = k;
   }
 }
 

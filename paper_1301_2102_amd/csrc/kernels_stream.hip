@@ -95,25 +95,24 @@ constexpr int flush_waves(int p) { return p <= 8 ? 1 : 3; }
 
 template <int P, typename T>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(P)))) void k_flush(const T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
-                                              T* __restrict__ X, int64_t row0, int64_t row1, int64_t kexp,
+                                              T* __restrict__ X, int64_t n, int64_t kexp,
                                               const DevState* __restrict__ st) {
-  const int fb = flush_buf(kexp, P);
-  if (st->flush_block[fb] != kexp || st->flush_len[fb] == 0) return;
+  if (st->flush_block != kexp || st->flush_len == 0) return;
   constexpr int S = group_len(P), R = ring_len(P);
-  const int m = st->flush_len[fb];
-  const bool keep_m = st->flush_keep[fb] != 0;
+  const int m = st->flush_len;
+  const bool keep_m = st->flush_keep != 0;
   const int64_t g = kexp - m;
   __shared__ T sY[3][S + 2][P * P];  // input blocks: V_{g+1+t} at t < m, M_g at S, M_{g-1} at S + 1
   for (int e = threadIdx.x; e < 3 * (S + 2) * P * P; e += WG) {
     const int o = e / ((S + 2) * P * P), b = (e / (P * P)) % (S + 2), rc = e % (P * P);
     const int src = b < S ? b : MAXS + (b - S);
-    sY[o][b][rc] = (b < m || b >= S) ? (T)st->Y[fb][o][src][(rc / P) * MAXP + rc % P] : T(0);
+    sY[o][b][rc] = (b < m || b >= S) ? (T)st->Y[o][src][(rc / P) * MAXP + rc % P] : T(0);
   }
   __syncthreads();
   T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
   T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
   const int64_t stride = (int64_t)gridDim.x * WG;
-  for (int64_t row = row0 + (int64_t)blockIdx.x * WG + threadIdx.x; row < row1; row += stride) {
+  for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
     asm volatile("" ::: "memory");
     T acc[3][P];
 #pragma unroll
@@ -330,12 +329,10 @@ hipError_t launch_pass2(int p, T* Vbase, size_t slot, T* bench, int64_t n, DevSt
 }
 
 template <typename T>
-hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot, T* X, int64_t row0, int64_t row1, int64_t k,
-                        const DevState* st, hipStream_t s) {
-  if (row1 <= row0) return hipSuccess;
-  const int g = stream_grid(row1 - row0);
-#define L5(P) \
-  hipLaunchKernelGGL((k_flush<P, T>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, row0, row1, k, st)
+hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot, T* X, int64_t n, int64_t k, const DevState* st,
+                        hipStream_t s) {
+  const int g = stream_grid(n);
+#define L5(P) hipLaunchKernelGGL((k_flush<P, T>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, n, k, st)
   BMR_DISPATCH_P(p, L5)
 #undef L5
   return hipGetLastError();
@@ -407,8 +404,7 @@ hipError_t launch_pattern_grad(int p, const bmr_csr_t& A, const double* Lam, con
 
 #define BMR_INSTANTIATE(T)                                                                                          \
   template hipError_t launch_pass2<T>(int, T*, size_t, T*, int64_t, DevState*, hipStream_t);                        \
-  template hipError_t launch_flush<T>(int, const T*, T*, size_t, T*, int64_t, int64_t, int64_t, const DevState*, \
-                                      hipStream_t);                                                             \
+  template hipError_t launch_flush<T>(int, const T*, T*, size_t, T*, int64_t, int64_t, const DevState*, hipStream_t); \
   template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                                  \
   template hipError_t launch_bench_init<T>(T*, int64_t, int, uint64_t, hipStream_t);                               \
   template hipError_t launch_coldots<T>(const T*, int, int, const T*, int, int, int64_t, double*, int, hipStream_t); \

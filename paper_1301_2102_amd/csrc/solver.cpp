@@ -381,90 +381,21 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   // after them; the flush checks the block number the band kernel recorded.
   const int grp = group_len(p);
   int64_t kq = 1;
-  auto flush = [&](int64_t kb) -> int {  // the whole flush, on the caller's stream
-    HIP_TRY(launch_flush<T>(r.p, r.V, r.M, r.slot, X, 0, r.n, kb, r.st, r.s));
-    return 0;
-  };
-  // Outside profiling, a group's flush runs in s row chunks on a second
-  // stream, one after pass 1 of each block of the next group: it then shares
-  // the GPU with the reduction and the band kernel, which leave it almost
-  // idle, instead of following pass 2 on the critical path.  The group's
-  // ring slots stay untouched until pass 2 of block g + 2s + 2 (ring of
-  // 2s + 2 blocks), which waits for the group's last chunk; its coefficients
-  // sit in their own buffer until the group after next ends.
-  const bool async = !prof;
-  hipStream_t fs = nullptr;
-  hipEvent_t fev_p1[8] = {}, fev_done[2] = {};
-  struct FlushGuard {
-    hipStream_t* s;
-    hipEvent_t *a, *b;
-    ~FlushGuard() {
-      if (*s) {
-        (void)hipStreamSynchronize(*s);
-        (void)hipStreamDestroy(*s);
-      }
-      for (int i = 0; i < 8; ++i)
-        if (a[i]) (void)hipEventDestroy(a[i]);
-      for (int i = 0; i < 2; ++i)
-        if (b[i]) (void)hipEventDestroy(b[i]);
-    }
-  } fguard{&fs, fev_p1, fev_done};
-  if (async) {
-    HIP_TRY(hipStreamCreateWithFlags(&fs, hipStreamNonBlocking));
-    for (int i = 0; i < 8; ++i) HIP_TRY(hipEventCreateWithFlags(&fev_p1[i], hipEventDisableTiming));
-    for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&fev_done[i], hipEventDisableTiming));
-  }
-  int64_t pend = 0;                // last block of the group whose chunks are being launched (0: none)
-  int pend_c = 0;                  // its next chunk
-  int64_t done_block[2] = {0, 0};  // group whose last chunk fev_done[b] follows
-  auto launch_chunk = [&]() -> int {
-    const int64_t r0 = r.n * pend_c / grp / 64 * 64;
-    const int64_t r1 = pend_c + 1 == grp ? r.n : r.n * (pend_c + 1) / grp / 64 * 64;
-    HIP_TRY(launch_flush<T>(r.p, r.V, r.M, r.slot, X, r0, r1, pend, r.st, fs));
-    if (++pend_c == grp) {
-      const int b = flush_buf(pend, p);
-      HIP_TRY(hipEventRecord(fev_done[b], fs));
-      done_block[b] = pend;
-      pend = 0;
-      pend_c = 0;
-    }
-    return 0;
-  };
-  auto drain = [&]() -> int {  // every chunk still to launch, then wait for them
-    if (!async) return 0;
-    while (pend) TRY(launch_chunk());
-    HIP_TRY(hipStreamSynchronize(fs));
+  auto flush = [&](int64_t kb) -> int {
+    HIP_TRY(launch_flush<T>(r.p, r.V, r.M, r.slot, X, r.n, kb, r.st, r.s));
     return 0;
   };
   auto enq = [&](int slot) -> int {
     for (int q = 0; q < batch; ++q, ++kq) {
       if (prof) HIP_TRY(hipEventRecord(pev[slot][0], r.s));
       HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
-      if (async && pend) {  // the next chunk of the previous group's flush
-        hipEvent_t e = fev_p1[kq % 8];
-        HIP_TRY(hipEventRecord(e, r.s));
-        HIP_TRY(hipStreamWaitEvent(fs, e, 0));
-        TRY(launch_chunk());
-      }
       if (prof) HIP_TRY(hipEventRecord(pev[slot][1], r.s));
       HIP_TRY(launch_reduce(r.part, r.n_wg, n_entries(r.p, r.nb), r.red, r.st, 1, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][2], r.s));
       HIP_TRY(launch_band(r.p, 0, r.nb, r.red, r.hist, r.st, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][3], r.s));
-      if (async) {  // pass 2 of block kq rewrites the first ring slot of the group ending at kq - s - 2
-        const int64_t ge = kq - grp - 2;
-        if (ge > 0 && ge % grp == 0 && done_block[flush_buf(ge, p)] == ge)
-          HIP_TRY(hipStreamWaitEvent(r.s, fev_done[flush_buf(ge, p)], 0));
-      }
       HIP_TRY(launch_pass2<T>(r.p, r.V, r.slot, r.bench, r.n, r.st, r.s));
-      if (kq % grp == 0) {
-        if (async) {
-          pend = kq;
-          pend_c = 0;
-        } else {
-          TRY(flush(kq));
-        }
-      }
+      if (kq % grp == 0) TRY(flush(kq));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][4], r.s));
     }
     HIP_TRY(hipMemcpyAsync(&pin[slot], r.st, sizeof(Ctl), hipMemcpyDeviceToHost, r.s));
@@ -490,7 +421,6 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     if (ctl.reason != REASON_EXPLICIT_QR) break;
 
     // ---- column-wise QR of block k (near-dependent candidates) ----------
-    TRY(drain());
     const int64_t k = ctl.k;
     HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
     HIP_TRY(hipStreamSynchronize(r.s));
@@ -523,17 +453,11 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   }
   HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
   HIP_TRY(hipStreamSynchronize(r.s));
-  TRY(drain());
-  // a stop inside a group: its search directions still go into X.  The
-  // finishing block is the state's k (not advanced past it; k2 is cleared
-  // by the halted kernels enqueued after the stop).
-  if (hs->reason == REASON_FINISHED) {
-    const int64_t kf = hs->k;
-    const int fb = flush_buf(kf, p);
-    if (hs->flush_block[fb] == kf && hs->flush_len[fb] > 0 && kf % grp != 0 && kf != last_explicit) {
-      TRY(flush(kf));
-      HIP_TRY(hipStreamSynchronize(r.s));
-    }
+  // a stop inside a group: its search directions still go into X
+  if (hs->reason == REASON_FINISHED && hs->flush_len > 0 && hs->flush_block % grp != 0 &&
+      hs->flush_block != last_explicit) {
+    TRY(flush(hs->flush_block));
+    HIP_TRY(hipStreamSynchronize(r.s));
   }
   if (res_hist && o.hist_cap > 0) {
     const int64_t rows = std::min<int64_t>(hs->j, o.hist_cap);

@@ -117,12 +117,12 @@ def test_stop_inside_a_block(stop):
     assert _relcols(X, ro.X) <= 1e-10
 
 
-@pytest.mark.parametrize("p,stops", [(4, [63, 64, 65, 127, 128, 129, 191]), (8, [127, 128, 129, 136]),
+@pytest.mark.parametrize("p,stops", [(4, [127, 128, 129, 255, 256, 257, 383]), (8, [255, 256, 257, 264]),
                                      (16, [63, 64, 65, 80])])
 def test_stop_at_group_boundaries(p, stops):
     """The search directions enter X once per group of group_len(p) blocks
-    (16 at p <= 8, 4 at p = 16) and where the iteration stops: stops at a
-    group's last block (its regular flush), inside it, and just after it
+    (32 at p = 4 and 8, 4 at p = 16) and where the iteration stops: stops at
+    a group's last block (its regular flush), inside it, and just after it
     (the flush of a partial group) give the oracle's iterate."""
     s = bmr.group_len(p)
     A = laplacian((10, 11, 12), 0.3)

@@ -49,15 +49,15 @@ def test_default_opts(lib):
 def test_workspace_bytes(lib):
     n, p = 2097152, 8
     ws = bmr.workspace_bytes(n, p)
-    # V ring of 2 group_len(p) + 2 = 34 slots (groups of 16 blocks at p = 8,
-    # two groups in flight), two search-direction blocks, the bench
+    # V ring of group_len(p) + 2 = 34 slots (groups of 32 blocks at p = 8),
+    # two search-direction blocks, the bench
     blocks = (34 + 2) * n * p * 8 + 2 * n * 8
     assert blocks < ws < blocks + (16 << 20)
     assert bmr.workspace_bytes(n, p, hist_cap=1000) >= ws + 1000 * p * 8
-    # the V ring has 2 group_len(p) + 2 slots at every p (ties the Python
+    # the V ring has group_len(p) + 2 slots at every p (ties the Python
     # mirror of the group length to the library's)
     for q in (1, 3, 9, 10, 12, 16):
-        bq = (2 * bmr.group_len(q) + 4) * n * q * 8 + 2 * n * 8
+        bq = (bmr.group_len(q) + 4) * n * q * 8 + 2 * n * 8
         assert bq < bmr.workspace_bytes(n, q) < bq + (16 << 20), q
     # mixed precision: FP32 rings and bench, FP32 matrix values, FP32 D, FP64 R
     nnz = 14581760
