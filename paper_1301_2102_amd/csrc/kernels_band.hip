@@ -1,5 +1,5 @@
-// Reduction of the pass-1 partial sums and the band kernel: one wavefront
-// that turns the p x p Gram products of a block iteration into the new block
+// Reduction of the pass-1 partial sums and the band kernel: one workgroup of
+// two wavefronts that turns the p x p Gram products of a block iteration into the new block
 // of the band Hessenberg matrix, reduces its p columns by Givens rotations,
 // updates the rotated right-hand-side window S-hat, records the residual
 // recurrence and decides whether to stop (Sections 3-5, Algorithm 7.1).
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64) void k_reduce(const double* __restrict__ part, 
   if (threadIdx.x == 0) red[e] = s;
 }
 
-// The band kernel runs as a single wavefront (64 lanes).  Its barriers only
+// Most of the band kernel runs on one wavefront.  Its barriers there only
 // have to order LDS accesses between the lanes of that wavefront, which the
 // LDS executes in issue order; __syncthreads() would add a workgroup-scope
 // fence, which waits for every outstanding global store (the R rows, Z, the
