@@ -26,9 +26,73 @@ namespace {
 constexpr int WG = 256;
 
 // Wavefronts per SIMD that pass 2 asks the compiler to fit: one lane holds
-// several p-wide rows, and without a bound the compiler spends up to 256
-// registers on them at large p (one wavefront per SIMD).
-constexpr int pass2_waves(int p, int esz) { return esz == 8 && p >= 12 ? 3 : 4; }
+// several p-wide rows (and a row of the staging tile), and without a bound
+// the compiler spends up to 256 registers on them at large p (one wavefront
+// per SIMD); the bounds below are the tightest that do not spill.
+constexpr int pass2_waves(int p, int esz) {
+  return esz == 8 ? (p >= 14 ? 2 : p >= 10 ? 3 : 4) : (p >= 15 ? 3 : 4);
+}
+
+// Ordering of LDS accesses between the lanes of one wavefront (the LDS
+// executes a wavefront's accesses in issue order).
+__device__ inline void lane_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wavefront's 64 consecutive p-wide rows (64p elements from src, the first
+// `count` of them valid) into one row per lane: load instruction k reads the
+// contiguous elements 64k .. 64k+63, so every instruction consumes whole
+// cache lines and the loads can carry the non-temporal hint, and the tile
+// (rows padded to p+1 elements) turns them into rows in LDS.  One lane per
+// row loading its own p values instead issues p loads that each touch a
+// strip of the tile's lines: 3.7 against 6.0 TB/s for two such streams in
+// and one out, caches cold.
+template <int P, typename T>
+__device__ __attribute__((always_inline)) inline void rows_in(const T* __restrict__ src, int count, T* tile,
+                                                               int lane, T (&x)[P]) {
+  T t[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int e = 64 * k + lane;
+    t[k] = e < count ? __builtin_nontemporal_load(src + e) : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int e = 64 * k + lane;
+    tile[(e / P) * (P + 1) + e % P] = t[k];
+  }
+  lane_sync();
+#pragma unroll
+  for (int c = 0; c < P; ++c) x[c] = tile[lane * (P + 1) + c];
+  lane_sync();
+}
+
+// The inverse of rows_in: one row per lane out to 64 consecutive rows.  NT:
+// non-temporal stores, for blocks no kernel reads soon; V_{k+1} keeps
+// ordinary stores, which leave it in the memory-side cache for the gathers
+// of the next pass 1.
+template <int P, bool NT, typename T>
+__device__ __attribute__((always_inline)) inline void rows_out(T* __restrict__ dst, int count, T* tile, int lane,
+                                                                const T (&x)[P]) {
+#pragma unroll
+  for (int c = 0; c < P; ++c) tile[lane * (P + 1) + c] = x[c];
+  lane_sync();
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int e = 64 * k + lane;
+    if (e < count) {
+      const T y = tile[(e / P) * (P + 1) + e % P];
+      if constexpr (NT) {
+        __builtin_nontemporal_store(y, dst + e);
+      } else {
+        dst[e] = y;
+      }
+    }
+  }
+  lane_sync();
+}
 
 template <int P, typename T>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(P, sizeof(T))))) void k_pass2(
@@ -37,6 +101,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
   if (k == 0) return;
   constexpr int R = ring_len(P);
   __shared__ T sA[P * P], sB[P * P], sBc[MAXB * P];
+  __shared__ T stile[WG / 64][64 * (P + 1)];
   for (int e = threadIdx.x; e < P * P; e += WG) {
     const int r = e / P, c = e % P, o = r * MAXP + c;
     sA[e] = (T)st->P2A[o];
@@ -47,18 +112,20 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
   const int nb = st->nb, taken = st->taken;
   const T* __restrict__ V = Vbase + (size_t)(k % R) * slot;
   T* __restrict__ Wn = Vbase + (size_t)((k + 1) % R) * slot;
+  const int lane = threadIdx.x & 63;
+  T* tile = stile[threadIdx.x >> 6];
 
+  // each wavefront takes 64 consecutive rows per step
   const int64_t stride = (int64_t)gridDim.x * WG;
-  for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
+  for (int64_t row0 = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63); row0 < n; row0 += stride) {
     // re-read the coefficients from LDS in every row rather than holding
     // them in registers for the whole loop
     asm volatile("" ::: "memory");
+    const int count = (int)((n - row0 < 64 ? n - row0 : 64) * P);
+    const int64_t row = row0 + lane;
     T v[P], w[P];
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      v[c] = V[row * P + c];
-      w[c] = Wn[row * P + c];
-    }
+    rows_in<P>(V + row0 * P, count, tile, lane, v);
+    rows_in<P>(Wn + row0 * P, count, tile, lane, w);
     // finish the band orthogonalisation: column l loses sum_r A_k(r, l) u_r,
     // then the earlier new vectors of its own block
 #pragma unroll
@@ -72,14 +139,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
       for (int r = 0; r < l; ++r) w[l] = fma(-w[r], sB[r * P + l], w[l]);
       w[l] = w[l] / sB[l * P + l];
     }
-#pragma unroll
-    for (int c = 0; c < P; ++c) Wn[row * P + c] = w[c];
+    rows_out<P, false>(Wn + row0 * P, count, tile, lane, w);
     // keep the unused substitutes orthogonal to the new basis vectors
-    for (int b = taken; b < nb; ++b) {
-      T gv = bench[row * nb + b];
+    if (row < n) {
+      for (int b = taken; b < nb; ++b) {
+        T gv = bench[row * nb + b];
 #pragma unroll
-      for (int l = 0; l < P; ++l) gv = fma(-w[l], sBc[b * P + l], gv);
-      bench[row * nb + b] = gv;
+        for (int l = 0; l < P; ++l) gv = fma(-w[l], sBc[b * P + l], gv);
+        bench[row * nb + b] = gv;
+      }
     }
   }
 }
