@@ -162,9 +162,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
 constexpr int flush_waves(int p) { return p <= 8 ? 1 : 3; }
 
 template <int P, typename T>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(P)))) void k_flush(const T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot,
-                                              T* __restrict__ X, int64_t n, int64_t kexp,
-                                              const DevState* __restrict__ st) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(P)))) void k_flush(
+    const T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot, T* __restrict__ X, int64_t n, int64_t kexp,
+    const DevState* __restrict__ st) {
   if (st->flush_block != kexp || st->flush_len == 0) return;
   constexpr int S = group_len(P), R = ring_len(P);
   const int m = st->flush_len;
@@ -177,55 +177,98 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
     sY[o][b][rc] = (b < m || b >= S) ? (T)st->Y[o][src][(rc / P) * MAXP + rc % P] : T(0);
   }
   __syncthreads();
-  T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
-  T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
-  const int64_t stride = (int64_t)gridDim.x * WG;
-  for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
-    asm volatile("" ::: "memory");
-    T acc[3][P];
+  // p > 8: each wavefront's 64 rows of every block move through an LDS tile
+  // (coalesced non-temporal loads and stores, as in pass 2): p = 16
+  // 0.420 -> 0.395 ms per block iteration with pass 2.  p <= 8: one row per
+  // lane; there the tile's LDS would cost a workgroup per CU (3 -> 2) and the
+  // staged form was slower (pass 2 + flush 0.114 -> 0.125 ms at p = 8).
+  if constexpr (P > 8) {
+    T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
+    T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
+    __shared__ T stile[WG / 64][64 * (P + 1)];
+    const int lane = threadIdx.x & 63;
+    T* tile = stile[threadIdx.x >> 6];
+    // each wavefront takes 64 consecutive rows per step; its rows of every
+    // block move through the LDS tile as in pass 2
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t row0 = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63); row0 < n; row0 += stride) {
+      asm volatile("" ::: "memory");
+      const int count = (int)((n - row0 < 64 ? n - row0 : 64) * P);
+      T acc[3][P];
+      rows_in<P>(X + row0 * P, count, tile, lane, acc[0]);
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-      acc[0][c] = X[row * P + c];
-      acc[1][c] = acc[2][c] = T(0);
-    }
-    // inputs i = 0 .. m + 1: V_{g+1+i} (i < m), M_g, M_{g-1}.  For p <= 8
-    // the loads of four input rows are issued before their FMAs, so that a
-    // lane has several loads in flight (0.71 -> 0.63 ms per group at 128^3,
-    // p = 8); at larger p one row at a time keeps the registers in bounds.
-    constexpr int U = P <= 8 ? 4 : 1;
-    for (int i0 = 0; i0 < m + 2; i0 += U) {
-      T x[U][P];
+      for (int c = 0; c < P; ++c) acc[1][c] = acc[2][c] = T(0);
+      // inputs i = 0 .. m + 1: V_{g+1+i} (i < m), M_g, M_{g-1}, one block at
+      // a time (registers)
+      for (int i = 0; i < m + 2; ++i) {
+        const T* src = i < m ? Vbase + (size_t)((g + 1 + i) % R) * slot : (i == m ? Mb : Ma);
+        T x[P];
+        rows_in<P>(src + row0 * P, count, tile, lane, x);
+        const int b = i < m ? i : S + (i - m);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u;
-        if (i < m + 2) {
-          const T* __restrict__ src =
-              i < m ? Vbase + (size_t)((g + 1 + i) % R) * slot : (i == m ? Mb : Ma);
+        for (int r = 0; r < P; ++r)
 #pragma unroll
-          for (int c = 0; c < P; ++c) x[u][c] = src[row * P + c];
-        }
+          for (int o = 0; o < 3; ++o)
+#pragma unroll
+            for (int c = 0; c < P; ++c) acc[o][c] = fma(x[r], sY[o][b][r * P + c], acc[o][c]);
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u;
-        if (i < m + 2) {
-          const int b = i < m ? i : S + (i - m);
-#pragma unroll
-          for (int r = 0; r < P; ++r)
-#pragma unroll
-            for (int o = 0; o < 3; ++o)
-#pragma unroll
-              for (int c = 0; c < P; ++c) acc[o][c] = fma(x[u][r], sY[o][b][r * P + c], acc[o][c]);
-        }
+      rows_out<P, true>(X + row0 * P, count, tile, lane, acc[0]);
+      if (keep_m) {
+        rows_out<P, true>(Ma + row0 * P, count, tile, lane, acc[1]);
+        rows_out<P, true>(Mb + row0 * P, count, tile, lane, acc[2]);
       }
     }
-#pragma unroll
-    for (int c = 0; c < P; ++c) X[row * P + c] = acc[0][c];
-    if (keep_m) {
+  } else {
+    T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
+    T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
+      asm volatile("" ::: "memory");
+      T acc[3][P];
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        Ma[row * P + c] = acc[1][c];
-        Mb[row * P + c] = acc[2][c];
+        acc[0][c] = X[row * P + c];
+        acc[1][c] = acc[2][c] = T(0);
+      }
+      // inputs i = 0 .. m + 1: V_{g+1+i} (i < m), M_g, M_{g-1}.  For p <= 8
+      // the loads of four input rows are issued before their FMAs, so that a
+      // lane has several loads in flight (0.71 -> 0.63 ms per group at 128^3,
+      // p = 8); at larger p one row at a time keeps the registers in bounds.
+      constexpr int U = P <= 8 ? 4 : 1;
+      for (int i0 = 0; i0 < m + 2; i0 += U) {
+        T x[U][P];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u;
+          if (i < m + 2) {
+            const T* __restrict__ src =
+                i < m ? Vbase + (size_t)((g + 1 + i) % R) * slot : (i == m ? Mb : Ma);
+#pragma unroll
+            for (int c = 0; c < P; ++c) x[u][c] = src[row * P + c];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u;
+          if (i < m + 2) {
+            const int b = i < m ? i : S + (i - m);
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+#pragma unroll
+              for (int o = 0; o < 3; ++o)
+#pragma unroll
+                for (int c = 0; c < P; ++c) acc[o][c] = fma(x[u][r], sY[o][b][r * P + c], acc[o][c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < P; ++c) X[row * P + c] = acc[0][c];
+      if (keep_m) {
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+          Ma[row * P + c] = acc[1][c];
+          Mb[row * P + c] = acc[2][c];
+        }
       }
     }
   }
