@@ -30,7 +30,7 @@ constexpr int WG = 256;
 // the compiler spends up to 256 registers on them at large p (one wavefront
 // per SIMD); the bounds below are the tightest that do not spill.
 constexpr int pass2_waves(int p, int esz) {
-  return esz == 8 ? (p >= 14 ? 2 : p >= 10 ? 3 : 4) : (p >= 15 ? 3 : 4);
+  return esz == 8 ? (p >= 14 ? 2 : p >= 10 ? 3 : 4) : 4;
 }
 
 // Ordering of LDS accesses between the lanes of one wavefront (the LDS
@@ -101,7 +101,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
   if (k == 0) return;
   constexpr int R = ring_len(P);
   __shared__ T sA[P * P], sB[P * P], sBc[MAXB * P];
-  __shared__ T stile[WG / 64][64 * (P + 1)];
   for (int e = threadIdx.x; e < P * P; e += WG) {
     const int r = e / P, c = e % P, o = r * MAXP + c;
     sA[e] = (T)st->P2A[o];
@@ -112,36 +111,72 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
   const int nb = st->nb, taken = st->taken;
   const T* __restrict__ V = Vbase + (size_t)(k % R) * slot;
   T* __restrict__ Wn = Vbase + (size_t)((k + 1) % R) * slot;
-  const int lane = threadIdx.x & 63;
-  T* tile = stile[threadIdx.x >> 6];
+  if constexpr (sizeof(T) == 8) {
+    __shared__ T stile[WG / 64][64 * (P + 1)];
+    const int lane = threadIdx.x & 63;
+    T* tile = stile[threadIdx.x >> 6];
 
-  // each wavefront takes 64 consecutive rows per step
-  const int64_t stride = (int64_t)gridDim.x * WG;
-  for (int64_t row0 = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63); row0 < n; row0 += stride) {
-    // re-read the coefficients from LDS in every row rather than holding
-    // them in registers for the whole loop
-    asm volatile("" ::: "memory");
-    const int count = (int)((n - row0 < 64 ? n - row0 : 64) * P);
-    const int64_t row = row0 + lane;
-    T v[P], w[P];
-    rows_in<P>(V + row0 * P, count, tile, lane, v);
-    rows_in<P>(Wn + row0 * P, count, tile, lane, w);
-    // finish the band orthogonalisation: column l loses sum_r A_k(r, l) u_r,
-    // then the earlier new vectors of its own block
+    // each wavefront takes 64 consecutive rows per step
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t row0 = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63); row0 < n; row0 += stride) {
+      // re-read the coefficients from LDS in every row rather than holding
+      // them in registers for the whole loop
+      asm volatile("" ::: "memory");
+      const int count = (int)((n - row0 < 64 ? n - row0 : 64) * P);
+      const int64_t row = row0 + lane;
+      T v[P], w[P];
+      rows_in<P>(V + row0 * P, count, tile, lane, v);
+      rows_in<P>(Wn + row0 * P, count, tile, lane, w);
+      // finish the band orthogonalisation: column l loses sum_r A_k(r, l) u_r,
+      // then the earlier new vectors of its own block
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
+      for (int l = 0; l < P; ++l) {
 #pragma unroll
-      for (int r = 0; r < P; ++r) w[l] = fma(-v[r], sA[r * P + l], w[l]);
+        for (int r = 0; r < P; ++r) w[l] = fma(-v[r], sA[r * P + l], w[l]);
+      }
+#pragma unroll
+      for (int l = 0; l < P; ++l) {
+#pragma unroll
+        for (int r = 0; r < l; ++r) w[l] = fma(-w[r], sB[r * P + l], w[l]);
+        w[l] = w[l] / sB[l * P + l];
+      }
+      rows_out<P, false>(Wn + row0 * P, count, tile, lane, w);
+      // keep the unused substitutes orthogonal to the new basis vectors
+      if (row < n) {
+        for (int b = taken; b < nb; ++b) {
+          T gv = bench[row * nb + b];
+#pragma unroll
+          for (int l = 0; l < P; ++l) gv = fma(-w[l], sBc[b * P + l], gv);
+          bench[row * nb + b] = gv;
+        }
+      }
     }
+  } else {
+    // FP32: one row per lane.  Its rows are half as wide, and the staged form
+    // (4-byte elements, twice the instructions) was slower: 40.1 -> 45.8 us
+    // at p = 8, against 90.0 -> 76.0 us in FP64.
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
+      asm volatile("" ::: "memory");
+      T v[P], w[P];
 #pragma unroll
-    for (int l = 0; l < P; ++l) {
+      for (int c = 0; c < P; ++c) {
+        v[c] = V[row * P + c];
+        w[c] = Wn[row * P + c];
+      }
 #pragma unroll
-      for (int r = 0; r < l; ++r) w[l] = fma(-w[r], sB[r * P + l], w[l]);
-      w[l] = w[l] / sB[l * P + l];
-    }
-    rows_out<P, false>(Wn + row0 * P, count, tile, lane, w);
-    // keep the unused substitutes orthogonal to the new basis vectors
-    if (row < n) {
+      for (int l = 0; l < P; ++l) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) w[l] = fma(-v[r], sA[r * P + l], w[l]);
+      }
+#pragma unroll
+      for (int l = 0; l < P; ++l) {
+#pragma unroll
+        for (int r = 0; r < l; ++r) w[l] = fma(-w[r], sB[r * P + l], w[l]);
+        w[l] = w[l] / sB[l * P + l];
+      }
+#pragma unroll
+      for (int c = 0; c < P; ++c) Wn[row * P + c] = w[c];
       for (int b = taken; b < nb; ++b) {
         T gv = bench[row * nb + b];
 #pragma unroll
@@ -177,12 +212,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
     sY[o][b][rc] = (b < m || b >= S) ? (T)st->Y[o][src][(rc / P) * MAXP + rc % P] : T(0);
   }
   __syncthreads();
-  // p > 8: each wavefront's 64 rows of every block move through an LDS tile
-  // (coalesced non-temporal loads and stores, as in pass 2): p = 16
+  // FP64 and p > 8: each wavefront's 64 rows of every block move through an
+  // LDS tile (coalesced non-temporal loads and stores, as in pass 2): p = 16
   // 0.420 -> 0.395 ms per block iteration with pass 2.  p <= 8: one row per
   // lane; there the tile's LDS would cost a workgroup per CU (3 -> 2) and the
   // staged form was slower (pass 2 + flush 0.114 -> 0.125 ms at p = 8).
-  if constexpr (P > 8) {
+  // FP32 keeps one row per lane, as in its pass 2.
+  if constexpr (P > 8 && sizeof(T) == 8) {
     T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
     T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
     __shared__ T stile[WG / 64][64 * (P + 1)];
