@@ -196,6 +196,33 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(pass2_waves(
 // three wavefronts per SIMD (unbounded, p = 16 took all 256 registers).
 constexpr int flush_waves(int p) { return p <= 8 ? 1 : 3; }
 
+// rows_in for U blocks at once: every load is issued before the first
+// transpose, so that a lane has U p-wide rows in flight.
+template <int P, int U, typename T>
+__device__ __attribute__((always_inline)) inline void rows_in_batch(const T* const (&src)[U], const bool (&use)[U],
+                                                                     int count, T* tile, int lane, T (&x)[U][P]) {
+  T t[U][P];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int e = 64 * k + lane;
+      t[u][k] = (use[u] && e < count) ? __builtin_nontemporal_load(src[u] + e) : T(0);
+    }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int e = 64 * k + lane;
+      tile[(e / P) * (P + 1) + e % P] = t[u][k];
+    }
+    lane_sync();
+#pragma unroll
+    for (int c = 0; c < P; ++c) x[u][c] = tile[lane * (P + 1) + c];
+    lane_sync();
+  }
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(P)))) void k_flush(
     const T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot, T* __restrict__ X, int64_t n, int64_t kexp,
@@ -205,6 +232,61 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
   const int m = st->flush_len;
   const bool keep_m = st->flush_keep != 0;
   const int64_t g = kexp - m;
+  T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
+  T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
+  if constexpr (sizeof(T) == 8 && P <= 8) {
+    // FP64, p <= 8: the rows move through the LDS tile as in pass 2, and the
+    // wave-uniform coefficients are read from the state record (scalar
+    // loads) rather than staged in LDS, which leaves the tile as the only
+    // LDS use and keeps the occupancy.  Two input blocks are in flight.
+    __shared__ T stile[WG / 64][64 * (P + 1)];
+    const int lane = threadIdx.x & 63;
+    T* tile = stile[threadIdx.x >> 6];
+    const double* __restrict__ Yg = &st->Y[0][0][0];
+    const int64_t stride = (int64_t)gridDim.x * WG;
+    for (int64_t row0 = (int64_t)blockIdx.x * WG + (threadIdx.x & ~63); row0 < n; row0 += stride) {
+      asm volatile("" ::: "memory");
+      const int count = (int)((n - row0 < 64 ? n - row0 : 64) * P);
+      T acc[3][P];
+      rows_in<P>(X + row0 * P, count, tile, lane, acc[0]);
+#pragma unroll
+      for (int c = 0; c < P; ++c) acc[1][c] = acc[2][c] = T(0);
+      constexpr int U = 2;
+      for (int i0 = 0; i0 < m + 2; i0 += U) {
+        const T* srcs[U];
+        bool use[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u;
+          use[u] = i < m + 2;
+          srcs[u] = (i < m ? Vbase + (size_t)((g + 1 + i) % R) * slot : (i == m ? Mb : Ma)) + row0 * P;
+        }
+        T x[U][P];
+        rows_in_batch<P, U>(srcs, use, count, tile, lane, x);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u;
+          if (i < m + 2) {
+            const int bs = i < m ? i : MAXS + (i - m);  // block of Y
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+#pragma unroll
+              for (int o = 0; o < 3; ++o)
+#pragma unroll
+                for (int c = 0; c < P; ++c)
+                  acc[o][c] = fma(x[u][r], Yg[((size_t)o * (MAXS + 2) + bs) * (MAXP * MAXP) + r * MAXP + c],
+                                  acc[o][c]);
+          }
+        }
+      }
+      rows_out<P, true>(X + row0 * P, count, tile, lane, acc[0]);
+      if (keep_m) {
+        rows_out<P, true>(Ma + row0 * P, count, tile, lane, acc[1]);
+        rows_out<P, true>(Mb + row0 * P, count, tile, lane, acc[2]);
+      }
+    }
+    return;
+  }
   __shared__ T sY[3][S + 2][P * P];  // input blocks: V_{g+1+t} at t < m, M_g at S, M_{g-1} at S + 1
   for (int e = threadIdx.x; e < 3 * (S + 2) * P * P; e += WG) {
     const int o = e / ((S + 2) * P * P), b = (e / (P * P)) % (S + 2), rc = e % (P * P);
@@ -219,8 +301,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
   // staged form was slower (pass 2 + flush 0.114 -> 0.125 ms at p = 8).
   // FP32 keeps one row per lane, as in its pass 2.
   if constexpr (P > 8 && sizeof(T) == 8) {
-    T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
-    T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
     __shared__ T stile[WG / 64][64 * (P + 1)];
     const int lane = threadIdx.x & 63;
     T* tile = stile[threadIdx.x >> 6];
@@ -255,8 +335,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
       }
     }
   } else {
-    T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
-    T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
     const int64_t stride = (int64_t)gridDim.x * WG;
     for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += stride) {
       asm volatile("" ::: "memory");
