@@ -2,7 +2,9 @@
 // column-wise QR path.
 //
 // Pass 2 touches every row once and keeps each row's p values in registers
-// (one lane per row): it finishes the orthogonalisation of the candidates,
+// (one lane per row; in FP64 the rows travel between HBM and the lanes
+// through an LDS tile, so that every load and store instruction covers
+// whole cache lines): it finishes the orthogonalisation of the candidates,
 //     W' = W - V_k A_k,  V_{k+1} = W' B_k^{-1}          (forward substitution),
 // and updates the substitute bench against V_{k+1} (Section 5.1).  The
 // search directions of eq. (4.1) and the iterate update of eq. (4.2) are
@@ -13,11 +15,12 @@
 // V_{g+1} .. V_{g+s} and of M_g, M_{g-1}, with p x p coefficients that the
 // band kernel forms by a backward recurrence.  Per block iteration this
 // reads and writes three n x p blocks (W, V_k in, V_{k+1} out) instead of
-// six, plus (s + 5) blocks once per group.
+// six, plus (s + 6) blocks once per group.
 // The p x p coefficient blocks come from the band kernel through the device
 // state and are staged in LDS once per workgroup, rounded to the storage type
 // T (double, or float in the inner solve of the mixed-precision solver, whose
-// row arithmetic then runs in FP32).
+// row arithmetic then runs in FP32); the FP64 flush for p <= 8 reads them
+// from the state with scalar loads instead.
 #include "bmr_internal.hpp"
 
 namespace bmr {
