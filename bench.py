@@ -72,31 +72,82 @@ def measured_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, B, tol, gpu_iters, sample_iters):
-    """The CPU oracle, single BLAS thread, timed over a bounded prefix of the
-    same solve and scaled to the GPU's band-iteration count."""
+    """The CPU oracle (numpy with every BLAS thread the process may use;
+    scipy's CSR product is single-threaded), timed over a bounded prefix of
+    the same solve and scaled to the GPU's band-iteration count."""
     import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
+        lim = threadpool_limits(threads)
     except Exception:  # pragma: no cover
         lim = None
     As = A.to_scipy()
     t0 = time.perf_counter()
     r = oracle.solve(As, B, tol=tol, max_iter=sample_iters)
     dt = time.perf_counter() - t0
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
+    if lim is not None and hasattr(lim, "unregister"):
+        lim.unregister()
     per_iter = dt / max(r.iters, 1)
+    p = B.shape[1]
     return {
-        "value": per_iter * gpu_iters,
+        "value": round(per_iter * gpu_iters, 1),
         "unit": "s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"first {r.iters} band iterations of the same solve ({dt:.1f} s, {per_iter*1e3:.1f} ms per "
-                   f"band iteration, numpy/scipy with one thread), scaled to the {gpu_iters} band iterations "
-                   f"the GPU needs"),
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+        "sample": (f"first {r.iters} band iterations ({r.iters // p} block iterations) of the same solve, "
+                   f"{dt:.1f} s, {per_iter*1e3:.1f} ms per band iteration, numpy BLAS on {threads} threads "
+                   f"(scipy CSR product single-threaded), scaled to the {gpu_iters} band iterations the GPU "
+                   f"needs"),
     }
+
+
+def throughput_leg(bmr, torch, name, dev, block_iters):
+    """Cost per block iteration on a workload that is not run to its
+    tolerance: FP64 and the FP32 inner solver, a fixed number of block
+    iterations each, kernel durations from the profiled runs."""
+    from workloads import workload
+    A, B, _, _ = workload(name)
+    n, p = B.shape
+    Ad = bmr.to_device(A, dev)
+    Bd = torch.from_numpy(B).to(dev)
+    cap = block_iters * p
+    out = {"workload": name, "n": n, "nnz": A.nnz, "p": p, "band_iters": cap}
+    for prec, esz in (("fp64", 8), ("mixed", 4)):
+        ws = torch.empty(bmr.workspace_bytes(n, p, nnz=A.nnz, precision=prec), dtype=torch.uint8, device=dev)
+        kw = dict(precision=prec, max_refine=1) if prec == "mixed" else {}
+        bmr.solve(Ad, Bd, tol=1e-30, max_iter=cap, workspace=ws, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = bmr.solve(Ad, Bd, tol=1e-30, max_iter=cap, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, pinfo = bmr.solve(Ad, Bd, tol=1e-30, max_iter=cap, workspace=ws, profile=True, **kw)
+        nb = kernel_bytes(A, p, 2, esz)
+        km = pinfo.kernel_ms
+        out["fp64" if prec == "fp64" else "fp32_inner"] = {
+            "ms_per_block_iter": round(1e3 * wall / max(info.block_iters, 1), 4),
+            "block_iters": info.block_iters,
+            "res_rec_max": float(info.res_rec.max()),
+            "kernels": {k: {"avg_ms": round(km[k], 5),
+                            "GB/s": round(nb[k] / (km[k] * 1e-3) / 1e9, 1) if k in nb else None}
+                        for k in ("pass1_spmm_gram", "reduce", "band", "pass2_update")}}
+        del ws
+    return out
 
 
 def main():
@@ -107,7 +158,9 @@ def main():
     ap.add_argument("--workload", default="lap3d-128-p8")
     ap.add_argument("--max-iter", type=int, default=0, help="override the band-iteration cap (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=32)
+    ap.add_argument("--cpu-sample-iters", type=int, default=400)
+    ap.add_argument("--rand-block-iters", type=int, default=200,
+                    help="block iterations of the random-matrix throughput leg (0: skip)")
     ap.add_argument("--spmm-reps", type=int, default=50)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for hardware byte counters)")
@@ -238,6 +291,11 @@ def main():
         log(f"[bench] mixed: {mixed}")
         del Xm, wsm
 
+    rand = None
+    if args.rand_block_iters > 0:
+        rand = throughput_leg(bmr, torch, "rand-1m-p16", dev, args.rand_block_iters)
+        log(f"[bench] random matrix: {rand}")
+
     if args.copy_ref_mib:
         src = torch.empty(args.copy_ref_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -272,11 +330,13 @@ def main():
         "block_iters": info.block_iters,
         "res_rec_max": float(info.res_rec.max()),
         "res_explicit_max": explicit,
+        "res_explicit_stats_max": float(info.res_explicit.max()),
         "roofline": roofline,
         "kernels": kernels,
         "spmm": spmm,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "random_matrix": rand,
     }
     print(json.dumps(out), flush=True)
 

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define BMR_VERSION 10100 /* 1.1.0 */
+#define BMR_VERSION 10200 /* 1.2.0 */
 #define BMR_MAX_P 16      /* largest block size p */
 #define BMR_MAX_BENCH 4   /* largest substitutes bench */
 
@@ -138,6 +138,10 @@ typedef struct bmr_stats {
   int32_t n_refine;        /* BMR_PREC_MIXED: refinement cycles run (inner solves) */
   double res_true[BMR_MAX_P]; /* BMR_PREC_MIXED: final explicit ||b_i - A x_i|| / ||b_i||
                                  in binary64 (also copied to res_rec); 0 for BMR_PREC_FP64 */
+  double res_explicit[BMR_MAX_P]; /* explicit ||b_i - A x_i|| / ||b_i|| of the returned X,
+                                     computed in binary64 after the iteration (one extra
+                                     operator application; Algorithm 7.1's output);
+                                     0 where b_i = 0 */
 } bmr_stats_t;
 
 /* Library version, BMR_VERSION of the build. */

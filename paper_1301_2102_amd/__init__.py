@@ -55,7 +55,8 @@ class _Stats(ctypes.Structure):
                 ("block_iters", ctypes.c_int64), ("n_explicit_qr", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("res_rec", ctypes.c_double * MAX_P), ("time_ms", ctypes.c_double),
                 ("t_kernel_ms", ctypes.c_double * 4), ("n_profiled", ctypes.c_int64),
-                ("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32), ("res_true", ctypes.c_double * MAX_P)]
+                ("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32), ("res_true", ctypes.c_double * MAX_P),
+                ("res_explicit", ctypes.c_double * MAX_P)]
 
 FLAG_PROFILE = 1
 PREC_FP64 = 0
@@ -195,6 +196,7 @@ class SolveInfo:
     precision: str = "fp64"
     n_refine: int = 0                  # refinement cycles (precision="mixed")
     res_true: Optional[np.ndarray] = None  # final explicit relative residual (precision="mixed")
+    res_explicit: Optional[np.ndarray] = None  # explicit ||b_i - A x_i|| / ||b_i|| of the returned X
 
     @property
     def status_name(self) -> str:
@@ -242,6 +244,7 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
     info = SolveInfo(int(stats.status), int(stats.band_iters), int(stats.block_iters), int(stats.n_replaced),
                      int(stats.n_explicit_qr), np.array(stats.res_rec[:p]), float(stats.time_ms))
     info.precision = precision
+    info.res_explicit = np.array(stats.res_explicit[:p])
     if precision == "mixed":
         info.n_refine = int(stats.n_refine)
         info.res_true = np.array(stats.res_true[:p])

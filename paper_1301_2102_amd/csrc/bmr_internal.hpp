@@ -33,7 +33,7 @@ __host__ __device__ constexpr int ring_len(int p) { return group_len(p) + 2; }
 enum : int {
   REASON_NONE = 0,
   REASON_FINISHED = 1,     // converged, max_iter or bench exhausted
-  REASON_EXPLICIT_QR = 2,  // the Gram QR of the new block was rejected; host runs it column-wise
+  REASON_EXPLICIT_QR = 2,  // the Gram QR of the new block was rejected: it runs column by column
   REASON_ERROR = 3,
 };
 
@@ -48,9 +48,9 @@ __host__ __device__ constexpr int off_a(int p) { return 3 * p * p; }
 __host__ __device__ constexpr int off_Wg(int p) { return 3 * p * p + p; }
 __host__ __device__ constexpr int off_Vg(int p, int nb) { return 3 * p * p + p + p * nb; }
 
-// Device-resident state of one solve.  Written by the host once, then only by
-// the single-workgroup band kernel (and by the host while the device loop is
-// halted for a column-wise QR).  Small matrices use a fixed stride MAXP:
+// Device-resident state of one solve.  Written by the host at set-up, then
+// only by the single-workgroup band kernel and the single-workgroup decision
+// kernels of the column-wise QR.  Small matrices use a fixed stride MAXP:
 // M[r * MAXP + c] is row r, column c (0-based).
 struct DevState {
   // ---- control --------------------------------------------------------
@@ -104,6 +104,20 @@ struct DevState {
   int64_t flush_block;  // g + m of the last group whose coefficients are in Y
   int flush_len;        // m
   int flush_keep;       // != 0: the flush also writes M_{g+m-1} and M_{g+m}
+  // ---- column-wise QR on the device (initial QR, rejected Gram route) ----
+  // The QR kernels read and write these between launches; the host only
+  // enqueues them.  qr_R collects the triangular factor (S at set-up, B_k in
+  // the loop), qr_ref the norms the dependence test compares against.
+  double qr_R[MAXP * MAXP];
+  double qr_ref[MAXP];
+  double qr_coef[MAXP + MAXB];  // coefficients of the next column update
+  double qr_div;                // divisor of the next normalisation
+  int qr_active;                // 0 once the bench ran out: later QR steps do nothing
+  int qr_need_bench;            // the current column is dependent: a substitute is needed
+  int qr_src;                   // 0: normalise the column itself, 1: take bench vector qr_b
+  int qr_b;
+  int qr_lcap;                  // first column without a basis vector (p when none)
+  int qr_error;                 // a non-finite norm was met
 };
 
 // Workspace carve-up (offsets into the caller's workspace).  The blocks V, M
@@ -118,6 +132,11 @@ struct Layout {
 };
 
 Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision);
+// R = B - A X (R may be NULL) and the column norms ||b_i - A x_i|| (host
+// output), with p * n_wg doubles of partial sums in part and p reduced sums in
+// red (device scratch); synchronises the stream.  0 or a bmr_status error.
+int residual_norms(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* part, int n_wg,
+                   double* red, hipStream_t s, double* norms);
 int pass1_grid(int64_t n, int p);  // the most pass-1 workgroups (sizes the partial sums)
 // The pass-1 workgroups of a solve in storage type T: one resident round on
 // the current device, at most pass1_grid(n, p).
@@ -148,16 +167,25 @@ template <typename T>
 hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s);
 template <typename T>
 hipError_t launch_bench_init(T* bench, int64_t n, int nb, uint64_t seed, hipStream_t s);
-// Column kernels of the column-wise (explicit) QR path, FP64 arithmetic.
+// Column-wise QR on the device (kernels_colqr.hip): the QR of the p columns
+// of D in place, written as a fixed launch sequence whose decisions (the
+// dependence test, the substitute taken, exhaustion) are taken by
+// single-workgroup kernels from device-resident sums, so the host never
+// waits inside it.  SETUP: the initial QR of B (reference norms qr_ref set
+// by the host), the factor left in qr_R.  LOOP: the new block of block
+// iteration k after a rejected Gram route: W -= V_k A_k first (A_k and the
+// reference norms ||A u_j|| from the state), and at the end B_k := qr_R, the
+// column cap and the counters go to the state and the device loop resumes.
+enum { QR_SETUP = 0, QR_LOOP = 1 };
+template <typename T>
+hipError_t launch_colqr(int p, int mode, T* D, const T* Vk, T* bench, int nb, int64_t n, double* part, int n_wg,
+                        DevState* st, hipStream_t s);
+int colqr_grid(int64_t n);
+// Column kernels of the set-up norms, FP64 arithmetic.
 //   coldots: part[wg * (m+1) + r] = sum_i X[i*ldx + r] * Y[i*ldy + yc] (r < m), last = sum Y^2
 template <typename T>
 hipError_t launch_coldots(const T* Y, int ldy, int yc, const T* X, int ldx, int m, int64_t n, double* part,
                           int n_wg, hipStream_t s);
-struct ColCoef { double c[MAXP]; };
-//   colop: D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef.c[r] * X[i*ldx + r]) / div
-template <typename T>
-hipError_t launch_colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m,
-                        ColCoef coef, double div, int64_t n, hipStream_t s);
 int coldots_grid(int64_t n);
 // Conversions of the mixed-precision solver: dst = (float)src; x += (double)d; dst = src.
 hipError_t launch_to_f32(const double* src, float* dst, size_t count, hipStream_t s);

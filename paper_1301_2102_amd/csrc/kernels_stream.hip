@@ -433,32 +433,23 @@ __global__ __launch_bounds__(WG) void k_coldots(const T* Y, int ldy, int yc, con
       if (r < m) acc[r] = fma((double)X[i * ldx + r], y, acc[r]);
     acc[MAXP] = fma(y, y, acc[MAXP]);
   }
-  __shared__ double sh[WG];
-  for (int r = 0; r <= m; ++r) {
-    const double a = (r < m) ? acc[r] : acc[MAXP];
-    sh[threadIdx.x] = a;
-    __syncthreads();
-    for (int o = WG / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
+  // wavefront sums by shuffles, then the four wavefronts in order; every
+  // index into acc is a constant after unrolling (no scratch)
+  __shared__ double sh[WG / 64][MAXP + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r <= MAXP; ++r) {
+    if (r < m || r == MAXP) {
+      double a = acc[r];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (lane == 0) sh[wave][r] = a;
     }
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * (m + 1) + r] = sh[0];
-    __syncthreads();
   }
-}
-
-// D[i*ldd + dc] = (S[i*lds + sc] - sum_{r<m} coef[r] * X[i*ldx + r]) / div,
-// evaluated in FP64 and rounded to T once.  D may be the same column as S (in
-// place) and X may be other columns of the same block, so none of the
-// pointers is restrict-qualified.
-template <typename T>
-__global__ void k_colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m, ColCoef coef,
-                        double div, int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double y = S[i * lds + sc];
-    for (int r = 0; r < m; ++r) y = fma(-coef.c[r], (double)X[i * ldx + r], y);
-    D[i * ldd + dc] = (T)(y / div);
+  __syncthreads();
+  if (threadIdx.x <= m) {
+    const int r = threadIdx.x < m ? threadIdx.x : MAXP;
+    part[(size_t)blockIdx.x * (m + 1) + threadIdx.x] = (sh[0][r] + sh[1][r]) + (sh[2][r] + sh[3][r]);
   }
 }
 
@@ -594,14 +585,6 @@ hipError_t launch_coldots(const T* Y, int ldy, int yc, const T* X, int ldx, int 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m, ColCoef coef,
-                        double div, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_colop<T>, dim3(stream_grid(n)), dim3(WG), 0, s, D, ldd, dc, S, lds, sc, X, ldx, m, coef, div,
-                     n);
-  return hipGetLastError();
-}
-
 hipError_t launch_to_f32(const double* src, float* dst, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_to_f32, dim3(flat_grid(count)), dim3(WG), 0, s, src, dst, count);
@@ -635,9 +618,7 @@ hipError_t launch_pattern_grad(int p, const bmr_csr_t& A, const double* Lam, con
   template hipError_t launch_flush<T>(int, const T*, T*, size_t, T*, int64_t, int64_t, const DevState*, hipStream_t); \
   template hipError_t launch_fill<T>(T*, size_t, T, hipStream_t);                                                  \
   template hipError_t launch_bench_init<T>(T*, int64_t, int, uint64_t, hipStream_t);                               \
-  template hipError_t launch_coldots<T>(const T*, int, int, const T*, int, int, int64_t, double*, int, hipStream_t); \
-  template hipError_t launch_colop<T>(T*, int, int, const T*, int, int, const T*, int, int, ColCoef, double, int64_t, \
-                                      hipStream_t);
+  template hipError_t launch_coldots<T>(const T*, int, int, const T*, int, int, int64_t, double*, int, hipStream_t);
 BMR_INSTANTIATE(double)
 BMR_INSTANTIATE(float)
 #undef BMR_INSTANTIATE

@@ -11,8 +11,10 @@
 // block iterations are enqueued back to back and the host only polls a small
 // status record (double-buffered, pinned) between batches.  When the band
 // kernel rejects the Gram route for a near-dependent block, the device loop
-// halts and the host runs that block's QR column by column (with the
-// dependence test and bench substitution of Section 5.1), then resumes.
+// halts; at its next poll the host enqueues that block's QR column by column
+// (kernels_colqr.hip: the dependence test and bench substitution of
+// Section 5.1 are decided on the device) and the rest of the block
+// iteration, and goes on enqueueing without waiting for any of it.
 //
 // The block-iteration driver is a template over the storage type of the
 // n-length data: double for BMR_PREC_FP64, float for the inner solves of
@@ -88,75 +90,12 @@ struct Run {
     }
     return 0;
   }
-  int colop(T* D, int ldd, int dc, const T* S, int lds, int sc, const T* X, int ldx, int m, const double* coef,
-            double div) {
-    ColCoef cc;
-    for (int r = 0; r < MAXP; ++r) cc.c[r] = (r < m) ? coef[r] : 0.0;
-    HIP_TRY(launch_colop<T>(D, ldd, dc, S, lds, sc, X, ldx, m, cc, div, n, s));
+  // Column-wise QR of the block D on the device (launches only).
+  int colqr(int mode, T* D, const T* Vk) {
+    HIP_TRY(launch_colqr<T>(p, mode, D, Vk, bench, nb, n, part, colqr_grid(n), st, s));
     return 0;
   }
 };
-
-// Column-wise QR of the p columns of D (in place, row-interleaved, stride p):
-// classical Gram-Schmidt applied twice against the columns already done,
-// dependence when the remainder norm is <= gamma * ref[l], substitution by
-// the next bench vector, and one Gram-Schmidt step of the unused bench
-// vectors against every new column.  Coefficients go to R (stride MAXP).
-// Returns 0, or BMR_BENCH_EXHAUSTED with *lcap = the dependent column, or an
-// error.
-template <typename T>
-int column_qr(Run<T>& r, T* D, const double* ref, double gamma, const double* bench_norm0, int* taken,
-              int* n_replaced, double* R, int* lcap) {
-  const int p = r.p, nb = r.nb;
-  double c[MAXP + 1];
-  *lcap = p;
-  for (int l = 0; l < p; ++l) {
-    for (int q = 0; q < MAXP; ++q) R[q * MAXP + l] = 0.0;
-    if (l > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        int e = r.coldots(D, p, l, D, p, l, c);
-        if (e) return e;
-        for (int q = 0; q < l; ++q) R[q * MAXP + l] += c[q];
-        e = r.colop(D, p, l, D, p, l, D, p, l, c, 1.0);
-        if (e) return e;
-      }
-    }
-    int e = r.coldots(D, p, l, (const T*)nullptr, 0, 0, c);
-    if (e) return e;
-    const double eta = sqrt(c[0]);
-    if (!isfinite(eta)) return BMR_NONFINITE;
-    if (eta <= gamma * ref[l]) {
-      R[l * MAXP + l] = 0.0;
-      bool ok = *taken < nb;
-      double gn = 0.0;
-      if (ok) {
-        e = r.coldots(r.bench, nb, *taken, (const T*)nullptr, 0, 0, c);
-        if (e) return e;
-        gn = sqrt(c[0]);
-        ok = gn > gamma * bench_norm0[*taken];
-      }
-      if (!ok) {
-        *lcap = l;
-        return BMR_BENCH_EXHAUSTED;
-      }
-      e = r.colop(D, p, l, r.bench, nb, *taken, nullptr, 0, 0, nullptr, gn);
-      if (e) return e;
-      ++*taken;
-      ++*n_replaced;
-    } else {
-      R[l * MAXP + l] = eta;
-      e = r.colop(D, p, l, D, p, l, nullptr, 0, 0, nullptr, eta);
-      if (e) return e;
-    }
-    for (int b = *taken; b < nb; ++b) {
-      e = r.coldots(r.bench, nb, b, D + l, p, 1, c);
-      if (e) return e;
-      e = r.colop(r.bench, nb, b, r.bench, nb, b, D + l, p, 1, c, 1.0);
-      if (e) return e;
-    }
-  }
-  return 0;
-}
 
 #define TRY(expr)              \
   do {                         \
@@ -177,6 +116,7 @@ Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int p
   L.off_red = off;
   off = align256(off + sizeof(double) * n_entries(MAXP, MAXB));
   size_t part = std::max<size_t>((size_t)n_entries(p, nb) * L.n_wg, (size_t)coldots_grid(n) * (MAXP + 1));
+  part = std::max<size_t>(part, (size_t)colqr_grid(n) * std::max(MAXP, MAXB));
   part = std::max<size_t>(part, (size_t)p * L.n_wg);
   L.off_part = off;
   off = align256(off + sizeof(double) * part);
@@ -201,6 +141,20 @@ Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int p
   return L;
 }
 
+// R = B - A X (R may be NULL) and the column norms: per-workgroup partial
+// sums (part: p * n_wg doubles of device scratch) added in a fixed order on
+// the device into red (p doubles), then copied to the host.
+int residual_norms(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* part, int n_wg,
+                   double* red, hipStream_t s, double* norms) {
+  HIP_TRY(launch_residual(p, *A, B, X, R, part, n_wg, s));
+  HIP_TRY(launch_reduce(part, n_wg, p, red, nullptr, 0, s));
+  double h[MAXP];
+  HIP_TRY(hipMemcpyAsync(h, red, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < p; ++c) norms[c] = sqrt(h[c]);
+  return 0;
+}
+
 }  // namespace bmr
 
 using namespace bmr;
@@ -221,17 +175,20 @@ bool csr_valid(const bmr_csr_t* A) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Two pinned status records per host thread, reused by every solve of that
-// thread (allocated once, never freed).
-Ctl* pinned_ctl() {
-  static thread_local Ctl* buf = nullptr;
-  if (!buf) {
+// The two pinned status records the host polls, allocated for one run of
+// the block-iteration driver and freed at its end.
+struct PinnedCtl {
+  Ctl* buf = nullptr;
+  PinnedCtl() {
     void* p = nullptr;
-    if (hipHostMalloc(&p, 2 * sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return nullptr;
-    buf = (Ctl*)p;
+    if (hipHostMalloc(&p, 2 * sizeof(Ctl), hipHostMallocDefault) == hipSuccess) buf = (Ctl*)p;
   }
-  return buf;
-}
+  ~PinnedCtl() {
+    if (buf) (void)hipHostFree(buf);
+  }
+  PinnedCtl(const PinnedCtl&) = delete;
+  PinnedCtl& operator=(const PinnedCtl&) = delete;
+};
 
 // Parameters and results of one run of the block-iteration driver.
 struct CoreParams {
@@ -246,6 +203,7 @@ struct CoreOut {
   int64_t j = 0, k = 0;
   int n_replaced = 0, n_explicit = 0;
   double rho[MAXP] = {};
+  double bnorm[MAXP] = {};  // ||b_i|| of the right-hand side solved
   double tk[4] = {0, 0, 0, 0};  // summed kernel times over n_prof block iterations
   int64_t n_prof = 0;
 };
@@ -287,6 +245,7 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     bnorm[i] = sqrt(c[0]);
     if (!isfinite(bnorm[i])) return BMR_NONFINITE;
     hs->beta[i] = o.beta_stop ? o.beta_stop[i] : bnorm[i];
+    out.bnorm[i] = bnorm[i];
   }
   for (int b = 0; b < nb; ++b) {
     TRY(r.coldots(r.bench, nb, b, (const T*)nullptr, 0, 0, c));
@@ -299,23 +258,27 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     out.n_explicit = hs->n_explicit;
     for (int i = 0; i < MAXP; ++i) out.rho[i] = (i < p && rho) ? rho[i] : 0.0;
   };
-  // initial QR of F_0 = B into V_1 (slot 1): copy (rounded to T), then column-wise CGS2
+  // initial QR of F_0 = B into V_1 (slot 1): copy (rounded to T), then
+  // column-wise CGS2 on the device against the reference norms ||b_i||
+  for (int i = 0; i < p; ++i) hs->qr_ref[i] = bnorm[i];
+  HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
   T* V1 = r.Vslot(1);
   if constexpr (sizeof(T) == sizeof(double)) {
     HIP_TRY(launch_copy(B, (double*)V1, (size_t)n * p, r.s));
   } else {
     HIP_TRY(launch_to_f32(B, V1, (size_t)n * p, r.s));
   }
-  double S[MAXP * MAXP];
-  int lcap = p;
-  int qr = column_qr(r, V1, bnorm, o.gamma, hs->bench_norm0, &hs->taken, &hs->n_replaced, S, &lcap);
-  if (qr == BMR_BENCH_EXHAUSTED) {
+  TRY(r.colqr(QR_SETUP, V1, nullptr));
+  HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
+  HIP_TRY(hipStreamSynchronize(r.s));
+  if (hs->qr_error) return BMR_NONFINITE;
+  if (hs->qr_lcap < p) {  // a dependent column found no substitute
     double one[MAXP];
     for (int i = 0; i < p; ++i) one[i] = hs->beta[i] > 0 ? 1.0 : 0.0;
     finish(0, 0, one);
     return BMR_BENCH_EXHAUSTED;
   }
-  if (qr) return qr;
+  const double* S = hs->qr_R;
   // S-hat = E_1 S; stopping test at j = 0
   double worst = 0.0;
   for (int cidx = 0; cidx < p; ++cidx) {
@@ -334,7 +297,8 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
 
   // ---- block iterations -------------------------------------------------
-  Ctl* pin = pinned_ctl();
+  PinnedCtl pinned;
+  Ctl* pin = pinned.buf;
   if (!pin) return BMR_HIP_ERROR;
   hipEvent_t ev[2];
   HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -417,39 +381,22 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
       if (prof) TRY(enq(cur ^ 1));
       cur ^= 1;
     }
-    HIP_TRY(hipStreamSynchronize(r.s));
-    if (ctl.reason != REASON_EXPLICIT_QR) break;
-
-    // ---- column-wise QR of block k (near-dependent candidates) ----------
-    const int64_t k = ctl.k;
-    HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
-    HIP_TRY(hipStreamSynchronize(r.s));
-    T* Wn = r.Vslot(k + 1);
-    const T* Vk = r.Vslot(k);
-    for (int l = 0; l < p; ++l) {
-      double a[MAXP];
-      for (int q = 0; q < p; ++q) a[q] = hs->Ak[q * MAXP + l];
-      TRY(r.colop(Wn, p, l, Wn, p, l, Vk, p, p, a, 1.0));
+    if (ctl.reason != REASON_EXPLICIT_QR) {
+      HIP_TRY(hipStreamSynchronize(r.s));
+      break;
     }
-    double Bk[MAXP * MAXP];
-    int taken = hs->taken, nrep = hs->n_replaced, cap = p;
-    int e = column_qr(r, Wn, hs->araw, o.gamma, hs->bench_norm0, &taken, &nrep, Bk, &cap);
-    if (e && e != BMR_BENCH_EXHAUSTED) return e;
-    for (int q = 0; q < MAXP * MAXP; ++q) hs->Bk[q] = Bk[q];
-    hs->taken = taken;
-    hs->n_replaced = nrep;
-    hs->n_explicit += 1;
-    hs->lcap = cap;
-    hs->cap_status = BMR_BENCH_EXHAUSTED;
-    hs->halt = 0;
-    hs->reason = REASON_NONE;
-    HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
+    // ---- column-wise QR of block k (near-dependent candidates) ----------
+    // Enqueued behind the iterations still in flight, which return at once
+    // while the loop is halted; the QR's last kernel resumes the loop, and
+    // the band kernel (told that B_k and V_{k+1} are done), pass 2 and the
+    // group's flush complete block k.  Nothing here waits for the device.
+    const int64_t k = ctl.k;
+    TRY(r.colqr(QR_LOOP, r.Vslot(k + 1), r.Vslot(k)));
     HIP_TRY(launch_band(r.p, 1, r.nb, r.red, r.hist, r.st, r.s));
     HIP_TRY(launch_pass2<T>(r.p, r.V, r.slot, r.bench, r.n, r.st, r.s));
     TRY(flush(k));
     last_explicit = k;
     kq = k + 1;
-    HIP_TRY(hipStreamSynchronize(r.s));
   }
   HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
   HIP_TRY(hipStreamSynchronize(r.s));
@@ -489,22 +436,6 @@ void bind(Run<T>& r, const bmr_csr_t* A, const T* val, int p, int nb, hipStream_
   r.slot = slot_elems(A->n, p);
 }
 
-// R = B - A X (R may be NULL) and the column norms, summed on the host in
-// workgroup order.  part: p * n_wg doubles of device scratch.
-int residual_norms(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* part, int n_wg,
-                   hipStream_t s, double* norms) {
-  HIP_TRY(launch_residual(p, *A, B, X, R, part, n_wg, s));
-  std::vector<double> h((size_t)p * n_wg);
-  HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  for (int c = 0; c < p; ++c) {
-    double t = 0.0;
-    for (int w = 0; w < n_wg; ++w) t += h[(size_t)c * n_wg + w];
-    norms[c] = sqrt(t);
-  }
-  return 0;
-}
-
 void fill_stats(bmr_stats_t* stats, int status, int p, const CoreOut& o) {
   if (!stats) return;
   memset(stats, 0, sizeof(*stats));
@@ -527,7 +458,14 @@ int solve_fp64(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_
                 (o.flags & BMR_FLAG_PROFILE) != 0, nullptr};
   CoreOut out;
   const int status = solve_core<double>(r, B, X, cp, out, res_hist);
-  if (status >= 0) fill_stats(stats, status, p, out);
+  if (status < 0) return status;
+  // the explicit residual of the result, reported beside the recurrence
+  // values (Algorithm 7.1's output)
+  double rn[MAXP];
+  TRY(residual_norms(A, B, X, p, nullptr, r.part, L.n_wg, r.red, s, rn));
+  fill_stats(stats, status, p, out);
+  if (stats)
+    for (int i = 0; i < p; ++i) stats->res_explicit[i] = out.bnorm[i] > 0 ? rn[i] / out.bnorm[i] : 0.0;
   return status;
 }
 
@@ -542,13 +480,14 @@ int solve_mixed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr
   float* D = (float*)(ws + L.off_D);
   double* R = (double*)(ws + L.off_R);
   double* part = (double*)(ws + L.off_part);
+  double* red = (double*)(ws + L.off_red);
   Run<float> r{};
   bind(r, A, (const float*)val32, p, o.n_bench, s, ws, L);
   HIP_TRY(launch_to_f32(A->val, val32, (size_t)A->nnz, s));
   HIP_TRY(launch_fill<double>(X, (size_t)n * p, 0.0, s));
 
   double beta[MAXP], rn[MAXP], stop[MAXP], rel[MAXP];
-  TRY(residual_norms(A, B, X, p, R, part, L.n_wg, s, beta));  // X = 0: R = B
+  TRY(residual_norms(A, B, X, p, R, part, L.n_wg, red, s, beta));  // X = 0: R = B
   for (int i = 0; i < p; ++i) {
     if (!isfinite(beta[i])) return BMR_NONFINITE;
     rn[i] = beta[i];
@@ -593,7 +532,7 @@ int solve_mixed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr
     for (int q = 0; q < 4; ++q) tot.tk[q] += out.tk[q];
     tot.n_prof += out.n_prof;
     HIP_TRY(launch_add_f32(X, D, (size_t)n * p, s));
-    TRY(residual_norms(A, B, X, p, R, part, L.n_wg, s, rn));
+    TRY(residual_norms(A, B, X, p, R, part, L.n_wg, red, s, rn));
     status = st == BMR_BENCH_EXHAUSTED ? BMR_BENCH_EXHAUSTED : BMR_MAX_ITER;
   }
   for (int i = 0; i < p; ++i) tot.rho[i] = rel[i];
@@ -601,7 +540,7 @@ int solve_mixed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr
   if (stats) {
     stats->precision = BMR_PREC_MIXED;
     stats->n_refine = cycles;
-    for (int i = 0; i < p; ++i) stats->res_true[i] = rel[i];
+    for (int i = 0; i < p; ++i) stats->res_true[i] = stats->res_explicit[i] = rel[i];
   }
   return status;
 }
@@ -716,7 +655,8 @@ int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, do
   const size_t need = L.off_part + sizeof(double) * (size_t)p * L.n_wg;
   if (workspace_bytes < need) return BMR_WORKSPACE_TOO_SMALL;
   double* part = (double*)((char*)workspace + L.off_part);
-  return residual_norms(A, B, X, p, R, part, L.n_wg, stream, norms) == 0 ? BMR_CONVERGED : BMR_HIP_ERROR;
+  double* red = (double*)((char*)workspace + L.off_red);
+  return residual_norms(A, B, X, p, R, part, L.n_wg, red, stream, norms) == 0 ? BMR_CONVERGED : BMR_HIP_ERROR;
 }
 
 }  // extern "C"

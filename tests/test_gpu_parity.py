@@ -1,12 +1,18 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
 
-Tolerances (derived from the oracle's own rounding-order floor: the oracle
-against itself on a row-permuted copy of the same system):
+Tolerances (the oracle's own rounding-order floor was measured first: the
+oracle against itself on row-permuted copies of the same system, where every
+inner product is summed in another order):
   * residual history rho_j / ||b_i||: |gpu - oracle| <= 1e-6 * oracle + 1e-13
     over the iterations before Lanczos loses global orthogonality;
-  * X: max_i ||x_i^gpu - x_i^orc|| / ||x_i^orc|| <= 1e-8 at a fixed j in that
-    range, and at convergence to the 1e-8 tolerance;
-  * structure (replacement counts, stopping status) exactly.
+  * X: max_i ||x_i^gpu - x_i^orc|| / ||x_i^orc|| <= 1e-8 at the same stopping
+    index j, both at a fixed j and at convergence (the permuted oracle agrees
+    with the oracle to <= 4e-13 at convergence on every small case here, with
+    the same stopping index);
+  * structure (replacement counts, stopping status, stopping index) exactly,
+    except on the 32 x 32 Laplacian, where the permuted oracles stop up to
+    STOP_FLOOR_LAP2D iterations apart: there both sides are rerun to the
+    smaller index and compared at it.
 """
 import numpy as np
 import pytest
@@ -29,8 +35,23 @@ def _dev(B):
     return torch.from_numpy(np.ascontiguousarray(B)).to(DEV)
 
 
+def _cols(ro, idx):
+    """The oracle result restricted to some columns of X."""
+    import copy
+    r = copy.copy(ro)
+    r.X = ro.X[:, idx]
+    return r
+
+
 def _relcols(X, Y):
     return (np.linalg.norm(X - Y, axis=0) / np.maximum(np.linalg.norm(Y, axis=0), 1e-300)).max()
+
+
+def _same_stop(A, B, X, info, ro, xtol=1e-8, **kw):
+    """Equal status and stopping index, and X to xtol there."""
+    assert info.status == ro.status, (info.status_name, ro.status)
+    assert info.band_iters == ro.iters, (info.band_iters, ro.iters)
+    assert _relcols(X, ro.X) <= xtol, _relcols(X, ro.X)
 
 
 def _hist_close(hg, ho, rel=1e-6, abs_=1e-13):
@@ -43,7 +64,7 @@ def _hist_close(hg, ho, rel=1e-6, abs_=1e-13):
 # ---------------------------------------------------------------------------
 # block operator
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8, 13, 16])
+@pytest.mark.parametrize("p", range(1, 17))
 @pytest.mark.parametrize("kind", ["lap", "rand"])
 def test_spmm_matches_scipy(p, kind):
     A = laplacian((17, 19, 23), 0.3) if kind == "lap" else random_symmetric(5003, draws=13, seed=2)
@@ -73,6 +94,11 @@ def _both(A, B, tol, max_iter, **kw):
     return Xg.cpu().numpy(), info, ro, Ad
 
 
+# Converged 32 x 32 solve: 19 row permutations of the oracle stop at
+# j = 658 .. 670 against the oracle's 670 (X within 6e-10 at the smaller index).
+STOP_FLOOR_LAP2D = 16
+
+
 def test_lap2d_32_p4_full_config():
     """2-D 5-point Laplacian 32x32, shift -0.7, n=1024, p=4, tol 1e-8, 500 iterations."""
     A, B, tol, mi = workload("lap2d-32-p4")
@@ -87,13 +113,20 @@ def test_lap2d_32_p4_full_config():
     assert _relcols(X250, r250.X) <= 1e-8
     Xc, ic, rc, Ad = _both(A, B, 1e-8, 5000)
     assert ic.status == rc.status == bmr.CONVERGED
-    assert abs(ic.band_iters - rc.iters) <= 40
-    assert _relcols(Xc, rc.X) <= 1e-8
+    assert abs(ic.band_iters - rc.iters) <= STOP_FLOOR_LAP2D, (ic.band_iters, rc.iters)
+    if ic.band_iters == rc.iters:
+        assert _relcols(Xc, rc.X) <= 1e-8
+    else:  # both sides again, stopped at the smaller index
+        jm = min(ic.band_iters, rc.iters)
+        Xm, im, rm, _ = _both(A, B, 1e-30, jm)
+        assert im.band_iters == rm.iters == jm
+        assert _relcols(Xm, rm.X) <= 1e-8
     ex = bmr.residual(Ad, _dev(B), _dev(Xc)) / ro.beta
     assert ex.max() < 5e-8
+    assert np.allclose(ic.res_explicit, ex, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 5, 8, 16])
+@pytest.mark.parametrize("p", range(1, 17))
 def test_block_sizes(p):
     A = laplacian((10, 11, 12), 0.3)
     B = rhs_normal(A.n, p, seed=p)
@@ -102,8 +135,8 @@ def test_block_sizes(p):
     _hist_close(info.hist, ro.hist)
     assert _relcols(X, ro.X) <= 1e-8
     Xc, ic, rc, _ = _both(A, B, 1e-9, 4000)
-    assert ic.status == rc.status == bmr.CONVERGED
-    assert _relcols(Xc, rc.X) <= 1e-7
+    assert ic.status == bmr.CONVERGED
+    _same_stop(A, B, Xc, ic, rc)
 
 
 @pytest.mark.parametrize("stop", [1, 5, 7, 8, 9, 13])
@@ -117,14 +150,18 @@ def test_stop_inside_a_block(stop):
     assert _relcols(X, ro.X) <= 1e-10
 
 
-@pytest.mark.parametrize("p,stops", [(4, [127, 128, 129, 255, 256, 257, 383]), (8, [255, 256, 257, 264]),
-                                     (16, [63, 64, 65, 80])])
-def test_stop_at_group_boundaries(p, stops):
+@pytest.mark.parametrize("p", range(1, 17))
+def test_stop_at_group_boundaries(p):
     """The search directions enter X once per group of group_len(p) blocks
-    (32 at p = 4 and 8, 4 at p = 16) and where the iteration stops: stops at
-    a group's last block (its regular flush), inside it, and just after it
-    (the flush of a partial group) give the oracle's iterate."""
+    (32 up to p = 8, 12 .. 4 above) and where the iteration stops: stops at
+    a group's last block (its regular flush), inside it, just after it (the
+    flush of a partial group) and inside the next group give the oracle's
+    iterate."""
     s = bmr.group_len(p)
+    g = s * p
+    stops = [g - 1, g, g + 1, g + p + p // 2]
+    if p in (4, 8):
+        stops += [2 * g - 1, 2 * g, 2 * g + 1]
     A = laplacian((10, 11, 12), 0.3)
     B = rhs_normal(A.n, p, seed=11 + p)
     for stop in stops:
@@ -148,7 +185,7 @@ def test_dependence_e1_ae1_in_iteration():
     assert np.linalg.norm(X[:, 1] - e1) <= 1e-12
     assert np.all(info.hist[:, 1] <= 1e-13)
     _hist_close(info.hist[:100], ro.hist[:100])
-    assert _relcols(X, ro.X) <= 1e-8
+    _same_stop(A, B, X, info, ro)
 
 
 def test_dependence_with_extra_columns():
@@ -156,8 +193,8 @@ def test_dependence_with_extra_columns():
     B = rhs_e1_ae1(A, extra=3, seed=4)
     X, info, ro, _ = _both(A, B, 1e-9, 3000)
     assert info.n_replaced == len(ro.replaced)
-    assert info.status == ro.status == bmr.CONVERGED
-    assert _relcols(X, ro.X) <= 1e-7
+    assert info.status == bmr.CONVERGED
+    _same_stop(A, B, X, info, ro)
 
 
 @pytest.mark.parametrize("k", [0, 4, 8])
@@ -165,9 +202,9 @@ def test_stress_copy_column(k):
     A = laplacian((16, 16, 16), 0.3)
     B = rhs_stress(A.n, k, p=8, seed=0)
     X, info, ro, _ = _both(A, B, 1e-8, 6000)
-    assert info.status == ro.status == bmr.CONVERGED
+    assert info.status == bmr.CONVERGED
     assert info.n_replaced == len(ro.replaced) >= 1
-    assert _relcols(X, ro.X) <= 1e-7
+    _same_stop(A, B, X, info, ro)
     assert np.linalg.norm(X[:, 7] - X[:, 0]) <= 1e-10 * np.linalg.norm(X[:, 0])
 
 
@@ -176,9 +213,10 @@ def test_zero_column_and_exhaustion():
     B = rhs_normal(A.n, 3, seed=2)
     B[:, 1] = 0.0
     X, info, ro, _ = _both(A, B, 1e-10, 2000)
-    assert info.status == ro.status == bmr.CONVERGED
+    assert info.status == bmr.CONVERGED
     assert np.all(X[:, 1] == 0.0)
-    assert _relcols(X[:, [0, 2]], ro.X[:, [0, 2]]) <= 1e-7
+    assert info.n_replaced == len(ro.replaced) == 1
+    _same_stop(A, B, X[:, [0, 2]], info, _cols(ro, [0, 2]))
     B2 = rhs_stress(A.n, 0, p=3, seed=2)
     X2, i2, r2, _ = _both(A, B2, 1e-10, 100, n_bench=0)
     assert i2.status == r2.status == bmr.BENCH_EXHAUSTED
@@ -215,11 +253,14 @@ def test_tiny_systems_and_zero_rhs():
 
 
 def test_full_size_lap3d_128_p8_prefix():
-    """128^3 Laplacian, p=8, the benchmark's launch configuration: the first 48
-    band iterations against the oracle element by element."""
+    """128^3 Laplacian, p=8, the benchmark's launch configuration: the first
+    264 band iterations against the oracle element by element (33 block
+    iterations: one whole group of 32 blocks with its regular flush at
+    j = 256, then a partial group flushed at the stop)."""
     A, B, _, _ = workload("lap3d-128-p8")
-    X, info, ro, _ = _both(A, B, 1e-30, 48)
-    assert info.band_iters == ro.iters == 48
+    X, info, ro, _ = _both(A, B, 1e-30, 264)
+    assert info.band_iters == ro.iters == 264
+    assert info.block_iters == 33
     _hist_close(info.hist, ro.hist)
     assert _relcols(X, ro.X) <= 1e-8
 
@@ -236,17 +277,19 @@ def test_full_size_lap3d_128_p8_converged_properties():
     ex = bmr.residual(Ad, Bd, X) / beta
     assert info.res_rec.max() < tol
     assert ex.max() < 10 * tol
+    assert np.allclose(info.res_explicit, ex, rtol=1e-12, atol=0)
     assert np.all(np.diff(info.hist, axis=0) <= 1e-14)
 
 
 @pytest.mark.parametrize("name", ["lap3d-128-p1", "lap3d-128-p16", "rand-1m-p16"])
 def test_full_size_prefix_other_workloads(name):
     """The other full-size workloads (128^3 at p = 1 and p = 16, the random
-    sparse indefinite matrix with n = 2^20, p = 16): the first 32 band
-    iterations against the oracle element by element."""
+    sparse indefinite matrix with n = 2^20, p = 16): the first 64 band
+    iterations against the oracle element by element (two groups of 4 blocks
+    at p = 16, two full groups at p = 1)."""
     A, B, _, _ = workload(name)
-    X, info, ro, _ = _both(A, B, 1e-30, 32)
-    assert info.band_iters == ro.iters == 32
+    X, info, ro, _ = _both(A, B, 1e-30, 64)
+    assert info.band_iters == ro.iters == 64
     _hist_close(info.hist, ro.hist)
     assert _relcols(X, ro.X) <= 1e-8
 
@@ -254,15 +297,15 @@ def test_full_size_prefix_other_workloads(name):
 @pytest.mark.parametrize("name", ["stress-64-k0", "stress-64-k4", "stress-64-k8", "stress-64-e3"])
 def test_full_size_stress_prefix(name):
     """64^3 deflation-stress inputs at full size: the replacements of the
-    first 48 band iterations (the copy column at the initial QR; the
+    first 64 band iterations (the copy column at the initial QR; the
     dependent candidate of iteration 1 for [e_1, A e_1, ...]) match the
     oracle, and so do the iterate and the residual history."""
     A, B, _, _ = workload(name)
-    X, info, ro, _ = _both(A, B, 1e-30, 48)
-    assert info.band_iters == ro.iters == 48
+    X, info, ro, _ = _both(A, B, 1e-30, 64)
+    assert info.band_iters == ro.iters == 64
     assert info.n_replaced == len(ro.replaced) >= 1
     _hist_close(info.hist, ro.hist)
-    assert _relcols(X, ro.X) <= 1e-7
+    assert _relcols(X, ro.X) <= 1e-8
 
 
 @pytest.mark.parametrize("name", ["stress-64-k0", "stress-64-k4", "stress-64-k8", "stress-64-e3"])
@@ -280,6 +323,7 @@ def test_full_size_stress_converged_properties(name):
     beta = np.linalg.norm(B, axis=0)
     ex = bmr.residual(Ad, Bd, X) / beta
     assert ex.max() < 10 * tol
+    assert np.allclose(info.res_explicit, ex, rtol=1e-12, atol=0)
     Xh = X.cpu().numpy()
     if name.endswith("e3"):
         e1 = np.zeros(A.n)

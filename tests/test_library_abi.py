@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.bmr_version() == 10100
+    assert lib.bmr_version() == 10200
     for code, word in [(0, "converged"), (1, "maximum"), (2, "bench"), (3, "stagnated"), (-1, "invalid"),
                        (-2, "workspace"), (-3, "HIP"), (-4, "non-finite"), (-5, "singular")]:
         assert word in bmr.status_string(code)
@@ -43,7 +43,7 @@ def test_default_opts(lib):
     lib.bmr_default_opts(ctypes.byref(o))
     assert (o.tol, o.max_iter, o.gamma, o.n_bench, o.seed, o.hist_cap, o.flags) == (1e-8, 10000, 1e-10, 2, 0, 0, 0)
     assert (o.precision, o.inner_tol, o.max_refine) == (bmr.PREC_FP64, 1e-6, 30)
-    assert ctypes.sizeof(bmr._Opts) == 72 and ctypes.sizeof(bmr._Stats) == 344  # sizeof in C
+    assert ctypes.sizeof(bmr._Opts) == 72 and ctypes.sizeof(bmr._Stats) == 472  # sizeof in C
 
 
 def test_workspace_bytes(lib):
