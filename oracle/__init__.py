@@ -18,7 +18,11 @@ over a brute-force band basis, classical MINRES at p = 1, the band Arnoldi
 relation, the worked replacement example of Section 5.1, the C_{pxp} layout
 of Section 7 and the dependence demonstration of Section 8.  The adjoint
 gradients of ``adjoint.py`` (an extension, not in the paper) are pinned by
-central finite differences of dense direct solves.
+central finite differences of dense direct solves.  The preconditioned solve
+of ``precond.py`` (IC(0) and split preconditioning; the paper's experiments
+precondition but do not say how) is pinned by dense Cholesky factors, the
+defining property of IC(0), a dense direct solve and scipy's preconditioned
+MINRES at p = 1 (``tests/test_oracle_precond.py``).
 """
 from .block_minres import (  # noqa: F401
     CONVERGED,
