@@ -225,6 +225,18 @@ int bmr_pattern_grad(const bmr_csr_t* A, const double* Lam, const double* X, int
 int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, double* R,
                  double* norms, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* The explicit residual of bmr_residual without a workspace, for callers that
+ * cannot allocate or pass device memory (code under graph capture, serving
+ * loops, harnesses that forbid allocation).  Same arguments and results as
+ * bmr_residual (the same kernels and summation order, so the same bits),
+ * with the partial sums in a static device array of the library: 2048 x 16
+ * partial sums + 16 reduced sums (262 KB per device, held until the process
+ * ends), enough for every valid n and p.  Calls no allocator.  Every call on
+ * a device shares that device's array: calls that overlap on one device (two
+ * streams, two host threads) race.  Synchronises the stream. */
+int bmr_residual_noalloc(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* norms,
+                         hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

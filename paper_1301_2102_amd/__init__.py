@@ -66,7 +66,7 @@ KERNEL_NAMES = ("pass1_spmm_gram", "reduce", "band", "pass2_update")
 
 
 EXPORTS = ("bmr_version", "bmr_status_string", "bmr_default_opts", "bmr_workspace_bytes", "bmr_solve",
-           "bmr_spmm", "bmr_spmm_f32", "bmr_pattern_grad", "bmr_residual")
+           "bmr_spmm", "bmr_spmm_f32", "bmr_pattern_grad", "bmr_residual", "bmr_residual_noalloc")
 
 _lib = None
 
