@@ -54,8 +54,32 @@ again where the code depends on it):
       taken into the basis is normalised.  With no vector left, or one whose
       norm has fallen to <= gamma times its initial norm, the solve stops with
       BENCH_EXHAUSTED and returns the last iterate.
-  R12 A removed candidate is discarded (Section 5.1's retained-vector variant
-      records no coefficients against it and would break A U = U H-bar).
+  R12 A removed candidate is discarded by default.  With ``retain=True``
+      (Section 5.1's last paragraph: a removed vector is kept, and new
+      Lanczos vectors are still orthogonalised against it until it would
+      have left the band) see R13.
+  R13 Retained removed vectors.  The removed candidate would have been basis
+      vector u_m; the new basis vectors whose window would have held it are
+      u_{m+1} .. u_{m+2p}.  Each of them, after the band orthogonalisation
+      (and after the CGS2 of the initial QR), takes one Gram-Schmidt step
+      against the retained vector, normalised, before its norm and the
+      dependence test; the coefficient is not recorded in H-bar (as the
+      paper says, this leaves the mathematical derivation).  A candidate is
+      retained only when its norm exceeds 2^-26 times the reference norm of
+      the dependence test: below that most of its direction is rounding
+      error (an exactly dependent candidate leaves only rounding noise), so
+      with the default gamma nothing is ever retained.
+  R14 Accumulated rotations (the remark of Section 4 on keeping the action
+      of a block of reflectors as one matrix applied by matrix products,
+      which the paper's own code does not do): with ``accumulate=True`` the
+      p^2 rotations of each complete block b of p columns are multiplied
+      into one orthogonal 2p x 2p matrix Q_b acting on the rows of blocks b
+      and b+1, and column j of block k applies Q_{k-2} and Q_{k-1} as
+      matrix-vector products before the rotations of the earlier columns of
+      its own block.  The rotations Q_{k-2} holds beyond those of columns
+      j-2p .. j-1 act on rows of column j that are still zero, so the
+      result is the sequential one in exact arithmetic; the rows above the
+      window stay exact zeros.
 """
 from __future__ import annotations
 
@@ -87,6 +111,7 @@ class Result:
     R: Optional[np.ndarray] = None       # (iters, iters) R_j (Givens form)
     Z: Optional[np.ndarray] = None       # (iters, p) rows z_j^T
     Xs: list = field(default_factory=list)  # X_1 .. X_j
+    retained: list = field(default_factory=list)  # R13: basis indices m of retained removed candidates
 
 
 def _givens(a: float, b: float):
@@ -98,14 +123,20 @@ def _givens(a: float, b: float):
     return a / r, b / r
 
 
+RETAIN_FLOOR = 2.0 ** -26   # R13: smallest retained norm, relative to the reference norm
+
+
 def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
-          n_bench: int = 2, seed: int = 0, record: bool = False) -> Result:
+          n_bench: int = 2, seed: int = 0, record: bool = False, retain: bool = False,
+          accumulate: bool = False) -> Result:
     """Solve A X = B (A symmetric, scipy CSR or anything with ``@``) by band-
     Lanczos block MINRES with X_0 = 0.
 
     ``tol`` is eps of Algorithm 7.1 relative to ||b_i||, ``max_iter`` is M (band
     iterations), ``gamma`` the relative dependence tolerance, ``n_bench`` and
-    ``seed`` the size and generator seed of the substitutes bench.
+    ``seed`` the size and generator seed of the substitutes bench; ``retain``
+    keeps removed candidates (R13); ``accumulate`` applies the rotations of
+    whole blocks as accumulated matrices (R14).
     """
     B = np.asarray(B, dtype=np.float64)
     if B.ndim != 2:
@@ -137,6 +168,21 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
 
     u = {}          # 1-based basis vectors u_i (a sliding window unless record)
     replaced = []
+    kept = []       # R13: (m, unit vector) of retained removed candidates
+
+    def project_kept(w, m_new):
+        # one Gram-Schmidt step of the new basis vector u_{m_new} against every
+        # retained vector whose band window would still hold it
+        for m, r in kept:
+            if m + 1 <= m_new <= m + 2 * p:
+                w -= (r @ w) * r
+
+    kept_at = []
+
+    def keep(m, w, nrm, ref):
+        if retain and nrm > RETAIN_FLOOR * ref:
+            kept.append((m, w / nrm))
+            kept_at.append(m)
 
     # ---- initial QR, F_0 = U_p S (eq. (3.2); R5) --------------------------
     S = np.zeros((p, p))
@@ -148,8 +194,10 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
                 c = Up.T @ w
                 S[:i, i] += c
                 w -= Up @ c
+        project_kept(w, i + 1)
         sigma = np.linalg.norm(w)
         if sigma <= gamma * beta[i]:
+            keep(i + 1, w, sigma, beta[i])
             S[i, i] = 0.0
             g = take_bench()
             if g is None:
@@ -180,6 +228,7 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
     h = {}          # band entries h[(row, col)] of H-bar (1-based)
     rcol = {}       # R columns, rcol[j] = {row: value}
     rot = {}        # rot[j] = [(c, s) for t = 1..p] acting on rows (j, j+t)
+    Qacc = {}       # R14: Qacc[b] = accumulated rotations of block b (2p x 2p)
     m = {}          # search directions m_i (window of 2p)
     zrows = []
     W = None
@@ -201,9 +250,11 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
         for i in range(j, j + p):                   # modified Gram-Schmidt
             h[(i, j)] = u[i] @ w
             w -= h[(i, j)] * u[i]
+        project_kept(w, j + p)                      # R13
         eta = np.linalg.norm(w)
         # -- dependence test and replacement (Section 5.1; R10) --
         if eta <= gamma * aw:
+            keep(j + p, w, eta, aw)
             h[(j + p, j)] = 0.0
             g = take_bench()
             if g is None:
@@ -222,10 +273,26 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
         r = {i: 0.0 for i in range(lo, j + p + 1)}
         for i in range(max(1, j - p), j + p + 1):
             r[i] = h[(i, j)]
-        for i in range(lo, j):                      # rotations of columns lo..j-1
+        kb = (j - 1) // p + 1                       # block of column j
+        own = range(lo, j)                          # columns whose rotations apply one by one
+        if accumulate:                              # R14
+            for i in range(max(1, (kb - 3) * p + 1), lo):
+                r[i] = 0.0
+            for b in (kb - 2, kb - 1):
+                if b >= 1:
+                    rows = range((b - 1) * p + 1, (b + 1) * p + 1)
+                    seg = Qacc[b] @ np.array([r[i] for i in rows])
+                    for i, v in zip(rows, seg):
+                        r[i] = v
+            own = range((kb - 1) * p + 1, j)
+        for i in own:                               # rotations of columns lo..j-1
             for t, (c, s) in enumerate(rot[i], start=1):
                 a, b = r[i], r[i + t]
                 r[i], r[i + t] = c * a + s * b, -s * a + c * b
+        if accumulate:
+            for i in range(max(1, (kb - 3) * p + 1), lo):
+                assert r[i] == 0.0, "rows above the band window must stay zero"
+                del r[i]
         rot[j] = []
         for t in range(1, p + 1):                   # new rotations zero rows j+1..j+p
             c, s = _givens(r[j], r[j + t])
@@ -236,6 +303,15 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
                 a, b = Shat[j].copy(), Shat[j + t].copy()
                 Shat[j], Shat[j + t] = c * a + s * b, -s * a + c * b
         rcol[j] = {i: r[i] for i in range(lo, j + 1)}
+        if accumulate and j % p == 0:               # block j/p complete: its rotations as one matrix
+            b, base = j // p, j - p + 1
+            Qb = np.eye(2 * p)
+            for i in range(base, j + 1):
+                for t, (c, s) in enumerate(rot[i], start=1):
+                    a, bb = Qb[i - base].copy(), Qb[i - base + t].copy()
+                    Qb[i - base], Qb[i - base + t] = c * a + s * bb, -s * a + c * bb
+            Qacc[b] = Qb
+            Qacc.pop(b - 2, None)
         if r[j] == 0.0:
             status = SINGULAR_R
             break
@@ -259,11 +335,13 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
             rot.pop(j - 2 * p, None)
             rcol.pop(j - 2 * p, None)
         m.pop(j - 2 * p, None)
+        kept[:] = [(mk, r) for mk, r in kept if mk + 2 * p > j + p]
         if hist[-1][live].max() < tol:
             status = CONVERGED
             break
 
     res = Result(X, status, j, beta, np.array(hist).reshape(-1, p), S, replaced)
+    res.retained = list(kept_at)
     if record:
         J = j
         res.U = np.column_stack([u[i] for i in sorted(u)])

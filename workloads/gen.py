@@ -145,6 +145,30 @@ def rhs_e1_ae1(A: Csr, extra: int = 0, seed: int = 0) -> np.ndarray:
     return np.ascontiguousarray(np.stack(cols, axis=1))
 
 
+def rhs_near_copy(n: int, p: int = 4, delta: float = 1e-5, seed: int = 3, pert_seed: int = 5) -> np.ndarray:
+    """N(0,1) columns with column 2 replaced by column 1 + delta * N(0,1): a
+    candidate that is dependent at the initial QR for a dependence tolerance
+    above about delta, with a remainder well above rounding."""
+    B = rhs_normal(n, p, seed=seed)
+    B[:, 1] = B[:, 0] + delta * np.random.default_rng(pert_seed).standard_normal(n)
+    return B
+
+
+def rhs_near_e1_ae1(A: Csr, delta: float = 1e-5, extra: int = 1, seed: int = 5) -> np.ndarray:
+    """[e_1, A e_1 + delta ||A e_1|| g / sqrt(n), N(0,1) ...] with g ~ N(0,1):
+    the candidate of the first band iteration lies within about delta of the
+    basis (near dependence inside the iteration)."""
+    n = A.n
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    Ae1 = A.column(0)
+    g = np.random.default_rng(seed).standard_normal(n)
+    cols = [e1, Ae1 + delta * np.linalg.norm(Ae1) * g / np.sqrt(n)]
+    if extra:
+        cols += [rhs_normal(n, 1, seed=9 + q)[:, 0] for q in range(extra)]
+    return np.ascontiguousarray(np.stack(cols, axis=1))
+
+
 def diag_positions(A: Csr) -> np.ndarray:
     """Index into A.data of the diagonal entry of every row (each row must
     store its diagonal)."""
