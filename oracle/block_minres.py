@@ -64,11 +64,18 @@ again where the code depends on it):
       (and after the CGS2 of the initial QR), takes one Gram-Schmidt step
       against the retained vector, normalised, before its norm and the
       dependence test; the coefficient is not recorded in H-bar (as the
-      paper says, this leaves the mathematical derivation).  A candidate is
-      retained only when its norm exceeds 2^-26 times the reference norm of
-      the dependence test: below that most of its direction is rounding
-      error (an exactly dependent candidate leaves only rounding noise), so
-      with the default gamma nothing is ever retained.
+      paper says, this leaves the mathematical derivation).  The substitute
+      that takes u_m's place (and any substitute taken while a retained
+      candidate's window is open, u_m included) also takes one Gram-Schmidt
+      step against it and is normalised again: the retained direction is
+      orthogonal to u_1 .. u_{m-1} (it is their remainder), so with the
+      substitute and the later vectors kept out of it the basis stays
+      orthonormal, and only the unrecorded coefficients are lost.  A
+      candidate is retained only when its norm exceeds 2^-26 times the
+      reference norm of the dependence test: below that most of its
+      direction is rounding error (an exactly dependent candidate leaves
+      only rounding noise), so with the default gamma nothing is ever
+      retained.
   R14 Accumulated rotations (the remark of Section 4 on keeping the action
       of a block of reflectors as one matrix applied by matrix products,
       which the paper's own code does not do): with ``accumulate=True`` the
@@ -179,8 +186,20 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
 
     kept_at = []
 
+    def substitute_out_of_kept(g, m):
+        # R13: a substitute taken as u_m while retained candidates apply to
+        # it (their window m_k .. m_k + 2p, m_k included) is kept out of them
+        hit = False
+        for mk, r in kept:
+            if mk <= m <= mk + 2 * p:
+                g = g - (r @ g) * r
+                hit = True
+        return g / np.linalg.norm(g) if hit else g
+
     def keep(m, w, nrm, ref):
-        if retain and nrm > RETAIN_FLOOR * ref:
+        # kept only when a substitute remains to take its place (otherwise the
+        # solve ends at this candidate anyway)
+        if retain and nrm > RETAIN_FLOOR * ref and taken < len(bench):
             kept.append((m, w / nrm))
             kept_at.append(m)
 
@@ -203,7 +222,7 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
             if g is None:
                 return Result(np.zeros((n, p)), BENCH_EXHAUSTED, 0, beta,
                               np.zeros((0, p)), S, replaced)
-            u[i + 1] = g
+            u[i + 1] = substitute_out_of_kept(g, i + 1)
             replaced.append(i + 1)
         else:
             S[i, i] = sigma
@@ -261,7 +280,7 @@ def solve(A, B, tol: float = 1e-8, max_iter: int = 1000, gamma: float = 1e-10,
                 status = BENCH_EXHAUSTED
                 j -= 1
                 break
-            u[j + p] = g
+            u[j + p] = substitute_out_of_kept(g, j + p)
             replaced.append(j + p)
         else:
             h[(j + p, j)] = eta
