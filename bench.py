@@ -150,6 +150,47 @@ def throughput_leg(bmr, torch, name, dev, block_iters):
     return out
 
 
+def precond_leg(bmr, torch, dims, sigma, p, tol, dev, orders):
+    """IC(0)-preconditioned solves of the headline system (factor of the
+    unshifted Laplacian) in the given unknown orderings: time to tol,
+    iterations, cost per block iteration and the explicit residual."""
+    from workloads import laplacian, permuted, redblack_order, rhs_normal
+    out = {}
+    for order in orders:
+        A = laplacian(dims, sigma)
+        M = laplacian(dims, 0.0)
+        if order == "redblack":
+            perm = redblack_order(dims)
+            A, M = permuted(A, perm), permuted(M, perm)
+        Ad = bmr.to_device(A, dev)
+        Md = bmr.to_device(M, dev)
+        B = torch.from_numpy(rhs_normal(A.n, p, seed=0)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ic = bmr.ic0_factor(Md)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        n = A.n
+        ws = torch.empty(bmr.workspace_bytes(n, p, precond="ic0"), dtype=torch.uint8, device=dev)
+        X = torch.empty_like(B)
+        bmr.solve(Ad, B, tol=1e-30, max_iter=8 * p, ic0=ic, workspace=ws, X=X)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = bmr.solve(Ad, B, tol=tol, max_iter=400000, ic0=ic, workspace=ws, X=X)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, pi = bmr.solve(Ad, B, tol=1e-30, max_iter=32 * p, ic0=ic, workspace=ws, profile=True)
+        out[order] = {"value": round(wall, 4), "unit": "s", "status": info.status_name,
+                      "band_iters": info.band_iters, "block_iters": info.block_iters,
+                      "ms_per_block_iter": round(1e3 * wall / max(info.block_iters, 1), 4),
+                      "factor_ms": round(1e3 * tf, 2), "res_rec_max": float(info.res_rec.max()),
+                      "res_explicit_max": float(info.res_explicit.max()),
+                      "operator_and_pass1_ms": round(pi.kernel_ms["pass1_spmm_gram"], 5),
+                      "pass2_ms": round(pi.kernel_ms["pass2_update"], 5)}
+        del Ad, Md, B, X, ic, ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +207,8 @@ def main():
                     help="also run a plain device copy of this many MiB (reference for hardware byte counters)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--inner-tol", type=float, default=1e-6)
+    ap.add_argument("--precond-orders", default="redblack",
+                    help="comma-separated unknown orderings of the IC(0) leg (natural, redblack; '' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
@@ -291,6 +334,12 @@ def main():
         log(f"[bench] mixed: {mixed}")
         del Xm, wsm
 
+    precond = None
+    orders = [o for o in args.precond_orders.split(",") if o]
+    if orders and args.workload.startswith("lap3d-128"):
+        precond = precond_leg(bmr, torch, (128, 128, 128), 0.3, p, tol, dev, orders)
+        log(f"[bench] ic0: {precond}")
+
     rand = None
     if args.rand_block_iters > 0:
         rand = throughput_leg(bmr, torch, "rand-1m-p16", dev, args.rand_block_iters)
@@ -337,6 +386,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "random_matrix": rand,
+        "ic0": precond,
     }
     print(json.dumps(out), flush=True)
 

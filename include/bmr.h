@@ -58,7 +58,8 @@ enum bmr_status {
   BMR_WORKSPACE_TOO_SMALL = -2,
   BMR_HIP_ERROR = -3,         /* a HIP runtime call failed */
   BMR_NONFINITE = -4,         /* NaN or Inf in B or in a computed coefficient */
-  BMR_SINGULAR_R = -5         /* a diagonal entry of the band QR factor R is zero */
+  BMR_SINGULAR_R = -5,        /* a diagonal entry of the band QR factor R is zero */
+  BMR_IC0_BREAKDOWN = -6      /* bmr_ic0_factor: a pivot of the incomplete factorisation was not positive */
 };
 
 /* Sparse symmetric matrix, CSR.  All pointers are device pointers. */
@@ -93,7 +94,8 @@ typedef struct bmr_opts {
                           (or below what the outer tolerance still needs).
                           0 < inner_tol < 1.  Default 1e-6. */
   int32_t max_refine;  /* BMR_PREC_MIXED: refinement cycles at most (>= 1).  Default 30. */
-  int32_t _reserved;
+  int32_t precond;     /* BMR_PRECOND_NONE (default) or BMR_PRECOND_IC0: sizes the workspace of
+                          bmr_workspace_bytes for bmr_solve_ic0 (bmr_solve accepts NONE only). */
 } bmr_opts_t;
 
 /* bmr_opts_t.precision.
@@ -114,10 +116,34 @@ typedef struct bmr_opts {
 #define BMR_PREC_FP64 0
 #define BMR_PREC_MIXED 1
 
+/* bmr_opts_t.precond. */
+#define BMR_PRECOND_NONE 0
+#define BMR_PRECOND_IC0 1
+
 /* bmr_opts_t.flags: time every kernel of every block iteration with HIP
  * events on the solve stream (one block iteration in flight at a time; the
  * averages go to bmr_stats_t.t_kernel_ms). */
 #define BMR_FLAG_PROFILE 1u
+
+/* bmr_opts_t.flags: keep removed candidates (Section 5.1, last paragraph).
+ * A candidate removed as dependent in place of basis vector u_m is kept,
+ * normalised, when its norm exceeds 2^-26 times the reference norm of the
+ * dependence test (below that most of its direction is rounding error, so
+ * with the default gamma nothing is kept), and the new basis vectors
+ * u_{m+1} .. u_{m+2p} (those whose band window would have held u_m) take one
+ * Gram-Schmidt step against it after their orthogonalisation against the
+ * band, with the coefficient not recorded in H-bar.  Blocks in such a window
+ * are orthogonalised column by column.  Sizes the workspace (n x n_bench
+ * more entries). */
+#define BMR_FLAG_RETAIN 2u
+
+/* bmr_opts_t.flags: apply the rotations of the two previous blocks to a new
+ * block's columns as accumulated matrices (Section 4's remark on keeping the
+ * action of a block of reflectors as one matrix, applied by matrix
+ * products): the p^2 Givens rotations of each block become one orthogonal
+ * 2p x 2p matrix.  The same iterate in exact arithmetic; only the rounding
+ * of the band factor changes. */
+#define BMR_FLAG_ACCUMULATE 4u
 
 /* Host-side result summary. */
 typedef struct bmr_stats {
@@ -142,6 +168,8 @@ typedef struct bmr_stats {
                                      computed in binary64 after the iteration (one extra
                                      operator application; Algorithm 7.1's output);
                                      0 where b_i = 0 */
+  int32_t n_retained;      /* BMR_FLAG_RETAIN: removed candidates kept */
+  int32_t _pad;
 } bmr_stats_t;
 
 /* Library version, BMR_VERSION of the build. */
@@ -236,6 +264,56 @@ int bmr_residual(const bmr_csr_t* A, const double* B, const double* X, int p, do
  * streams, two host threads) race.  Synchronises the stream. */
 int bmr_residual_noalloc(const bmr_csr_t* A, const double* B, const double* X, int p, double* R, double* norms,
                          hipStream_t stream);
+
+/* ---- IC(0) preconditioning --------------------------------------------
+ *
+ * The paper's experiments precondition with the incomplete Cholesky factor
+ * of the Laplacian part of the matrix (Section 8), without saying how the
+ * preconditioner enters Algorithm 7.1.  Here: M = C C^T with C the IC(0)
+ * factor of a symmetric matrix M (C lower triangular with the pattern of the
+ * lower triangle of M, (C C^T)_{ij} = M_{ij} on that pattern), and split
+ * preconditioning: block MINRES on C^{-1} A C^{-T} with right-hand sides
+ * C^{-1} B, then X = C^{-T} X-hat.  Column i of the iterate minimises
+ * ||C^{-1} (b_i - A x)|| over the preconditioned block Krylov space (for
+ * p = 1 the iterates of MINRES preconditioned with M^{-1}).
+ *
+ * The factor lives in a caller-owned device buffer (the "IC(0) object").
+ * Its set-up reads the pattern of M on the host once (integer work: the
+ * strictly lower pattern, the level of every row for the level-scheduled
+ * factorisation and solves, the transposed pattern); the factorisation and
+ * every triangular solve run on the device. */
+
+/* Device bytes of an IC(0) object for a matrix with n rows and nnz stored
+ * entries.  bytes: host output. */
+int bmr_ic0_bytes(int64_t n, int64_t nnz, size_t* bytes);
+
+/* Set up the IC(0) object of M in buf and factorise M on the device.
+ *   M      host pointer to a bmr_csr_t on the device; symmetric, every
+ *          diagonal entry stored, column indices sorted and unique.
+ *   buf    device, >= bmr_ic0_bytes(M->n, M->nnz) bytes, 256-byte aligned,
+ *          owned by the caller; it must outlive every use of the object.
+ * Synchronises the stream.  Returns BMR_IC0_BREAKDOWN when a pivot is not
+ * positive (IC(0) does not exist for every symmetric positive definite M;
+ * it does for M-matrices such as Laplacians), BMR_INVALID_ARG for a
+ * malformed pattern or a missing diagonal entry. */
+int bmr_ic0_factor(const bmr_csr_t* M, void* buf, size_t bytes, hipStream_t stream);
+
+/* W = C^{-1} V (trans = 0, forward substitution) or W = C^{-T} V (trans != 0,
+ * backward substitution) for the factor in the IC(0) object ic0; V, W device
+ * n x p row-interleaved (W may be V).  Asynchronous after reading the
+ * object's header. */
+int bmr_ic0_apply(const void* ic0, const double* V, double* W, int p, int trans, hipStream_t stream);
+
+/* Solve A X = B (X_0 = 0) by block MINRES with the split IC(0)
+ * preconditioner of the object ic0 (n must match A).  Arguments as in
+ * bmr_solve, binary64 only; the workspace must hold
+ * bmr_workspace_bytes(n, nnz, p, opts with precond = BMR_PRECOND_IC0) bytes;
+ * X must not alias B.  The stopping test, res_rec and the history refer to
+ * the preconditioned residual ||C^{-1}(b_i - A x_i)|| / ||C^{-1} b_i||;
+ * res_explicit is ||b_i - A x_i|| / ||b_i||. */
+int bmr_solve_ic0(const bmr_csr_t* A, const void* ic0, const double* B, double* X, int p, const bmr_opts_t* opts,
+                  void* workspace, size_t workspace_bytes, hipStream_t stream, bmr_stats_t* stats,
+                  double* res_hist);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,7 @@ WORKSPACE_TOO_SMALL = -2
 HIP_ERROR = -3
 NONFINITE = -4
 SINGULAR_R = -5
+IC0_BREAKDOWN = -6
 
 
 class _Csr(ctypes.Structure):
@@ -47,7 +48,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("gamma", ctypes.c_double),
                 ("n_bench", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("hist_cap", ctypes.c_int64), ("flags", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("_reserved", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -56,17 +57,24 @@ class _Stats(ctypes.Structure):
                 ("res_rec", ctypes.c_double * MAX_P), ("time_ms", ctypes.c_double),
                 ("t_kernel_ms", ctypes.c_double * 4), ("n_profiled", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32), ("res_true", ctypes.c_double * MAX_P),
-                ("res_explicit", ctypes.c_double * MAX_P)]
+                ("res_explicit", ctypes.c_double * MAX_P), ("n_retained", ctypes.c_int32), ("_pad", ctypes.c_int32)]
 
 FLAG_PROFILE = 1
+FLAG_RETAIN = 2
+FLAG_ACCUMULATE = 4
 PREC_FP64 = 0
 PREC_MIXED = 1
 _PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 KERNEL_NAMES = ("pass1_spmm_gram", "reduce", "band", "pass2_update")
 
 
+PRECOND_NONE = 0
+PRECOND_IC0 = 1
+_PRECONDS = {"none": PRECOND_NONE, "ic0": PRECOND_IC0}
+
 EXPORTS = ("bmr_version", "bmr_status_string", "bmr_default_opts", "bmr_workspace_bytes", "bmr_solve",
-           "bmr_spmm", "bmr_spmm_f32", "bmr_pattern_grad", "bmr_residual", "bmr_residual_noalloc")
+           "bmr_spmm", "bmr_spmm_f32", "bmr_pattern_grad", "bmr_residual", "bmr_residual_noalloc", "bmr_ic0_bytes", "bmr_ic0_factor",
+           "bmr_ic0_apply", "bmr_solve_ic0")
 
 _lib = None
 
@@ -99,6 +107,15 @@ def load(path: str = LIB_PATH):
     lib.bmr_pattern_grad.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp, vp]
     lib.bmr_residual.restype = i32
     lib.bmr_residual.argtypes = [ctypes.POINTER(_Csr), vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+    lib.bmr_ic0_bytes.restype = i32
+    lib.bmr_ic0_bytes.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    lib.bmr_ic0_factor.restype = i32
+    lib.bmr_ic0_factor.argtypes = [ctypes.POINTER(_Csr), vp, sz, vp]
+    lib.bmr_ic0_apply.restype = i32
+    lib.bmr_ic0_apply.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.bmr_solve_ic0.restype = i32
+    lib.bmr_solve_ic0.argtypes = [ctypes.POINTER(_Csr), vp, vp, vp, i32, ctypes.POINTER(_Opts), vp, sz, vp,
+                                  ctypes.POINTER(_Stats), vp]
     _lib = lib
     return lib
 
@@ -172,9 +189,11 @@ def _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, flags=0, pr
 
 
 def workspace_bytes(n: int, p: int, n_bench: int = 2, hist_cap: int = 0, nnz: int = 0,
-                    precision: str = "fp64") -> int:
-    """Device workspace bytes of a solve (nnz matters for precision="mixed")."""
-    o = _opts(1e-8, 1, 1e-10, n_bench, 0, hist_cap, 0, precision=precision)
+                    precision: str = "fp64", precond: str = "none", retain: bool = False) -> int:
+    """Device workspace bytes of a solve (nnz matters for precision="mixed";
+    precond="ic0" for a preconditioned solve; retain for kept candidates)."""
+    o = _opts(1e-8, 1, 1e-10, n_bench, 0, hist_cap, 0, flags=FLAG_RETAIN if retain else 0, precision=precision)
+    o.precond = _PRECONDS[precond]
     out = ctypes.c_size_t()
     st = load().bmr_workspace_bytes(int(n), int(nnz), int(p), ctypes.byref(o), ctypes.byref(out))
     if st != 0:
@@ -197,22 +216,70 @@ class SolveInfo:
     n_refine: int = 0                  # refinement cycles (precision="mixed")
     res_true: Optional[np.ndarray] = None  # final explicit relative residual (precision="mixed")
     res_explicit: Optional[np.ndarray] = None  # explicit ||b_i - A x_i|| / ||b_i|| of the returned X
+    n_retained: int = 0                # removed candidates kept (retain=True)
 
     @property
     def status_name(self) -> str:
         return status_string(self.status)
 
 
+class Ic0:
+    """An IC(0) factor on the device (bmr_ic0_factor of M); holds its buffer."""
+
+    def __init__(self, buf, n: int):
+        self.buf = buf
+        self.n = n
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+def ic0_factor(M: DeviceCsr) -> Ic0:
+    """Set up and factorise IC(0) of the symmetric matrix M on M's device."""
+    import torch
+    lib = load()
+    need = ctypes.c_size_t()
+    st = lib.bmr_ic0_bytes(M.n, M.nnz, ctypes.byref(need))
+    if st != 0:
+        raise BmrError(st, "bmr_ic0_bytes")
+    buf = torch.empty(int(need.value), dtype=torch.uint8, device=M.val.device)
+    Mc = M._c()
+    st = lib.bmr_ic0_factor(ctypes.byref(Mc), buf.data_ptr(), buf.numel(), _stream_handle(M.val.device))
+    if st != 0:
+        raise BmrError(st, "bmr_ic0_factor")
+    return Ic0(buf, M.n)
+
+
+def ic0_apply(ic0: Ic0, V, trans: bool = False, W=None):
+    """W = C^{-1} V (or C^{-T} V with trans) for the IC(0) factor C."""
+    import torch
+    _check_block(V, ic0.n, "V")
+    if W is None:
+        W = torch.empty_like(V)
+    st = load().bmr_ic0_apply(ic0.ptr, V.data_ptr(), W.data_ptr(), int(V.shape[1]), int(bool(trans)),
+                              _stream_handle(V.device))
+    if st != 0:
+        raise BmrError(st, "bmr_ic0_apply")
+    return W
+
+
 def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: float = 1e-10, n_bench: int = 2,
           seed: int = 0, hist_cap: int = 0, poll_every: int = 0, X=None, workspace=None, check: bool = True,
           profile: bool = False, precision: str = "fp64", inner_tol: Optional[float] = None,
-          max_refine: Optional[int] = None):
+          max_refine: Optional[int] = None, ic0: Optional[Ic0] = None, retain: bool = False,
+          accumulate: bool = False):
     """Solve A X = B (A symmetric) by band-Lanczos block MINRES on the GPU.
 
     B: contiguous float64 (n, p) CUDA tensor.  Returns (X, SolveInfo).
     precision="mixed" runs the FP32 inner solver inside FP64 iterative
     refinement (inner_tol, max_refine: see bmr_opts_t); its hist rows are the
-    explicit relative residuals after each refinement cycle.
+    explicit relative residuals after each refinement cycle.  ``retain``
+    keeps removed candidates (BMR_FLAG_RETAIN), ``accumulate`` applies the
+    previous blocks' rotations as accumulated matrices (BMR_FLAG_ACCUMULATE).
+    With ``ic0``
+    (from ic0_factor) the solve is split-preconditioned (bmr_solve_ic0; the
+    history and res_rec then refer to the preconditioned residual).
     Errors (negative status) raise BmrError when ``check`` is true.
     """
     import torch
@@ -223,8 +290,12 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
     if X is None:
         X = torch.empty_like(B)
     _check_block(X, n, "X")
-    o = _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, FLAG_PROFILE if profile else 0,
+    o = _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every,
+              (FLAG_PROFILE if profile else 0) | (FLAG_RETAIN if retain else 0)
+              | (FLAG_ACCUMULATE if accumulate else 0),
               precision, inner_tol, max_refine)
+    if ic0 is not None:
+        o.precond = PRECOND_IC0
     need = ctypes.c_size_t()
     st = lib.bmr_workspace_bytes(n, A.nnz, p, ctypes.byref(o), ctypes.byref(need))
     if st != 0:
@@ -236,15 +307,21 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
     hist = np.zeros((max(hist_cap, 0), p)) if hist_cap > 0 else None
     stats = _Stats()
     Ac = A._c()
-    st = lib.bmr_solve(ctypes.byref(Ac), B.data_ptr(), X.data_ptr(), p, ctypes.byref(o), workspace.data_ptr(),
-                       workspace.numel(), _stream_handle(B.device), ctypes.byref(stats),
-                       hist.ctypes.data if hist is not None else None)
+    hp = hist.ctypes.data if hist is not None else None
+    if ic0 is not None:
+        st = lib.bmr_solve_ic0(ctypes.byref(Ac), ic0.ptr, B.data_ptr(), X.data_ptr(), p, ctypes.byref(o),
+                               workspace.data_ptr(), workspace.numel(), _stream_handle(B.device),
+                               ctypes.byref(stats), hp)
+    else:
+        st = lib.bmr_solve(ctypes.byref(Ac), B.data_ptr(), X.data_ptr(), p, ctypes.byref(o), workspace.data_ptr(),
+                           workspace.numel(), _stream_handle(B.device), ctypes.byref(stats), hp)
     if st < 0 and check:
         raise BmrError(st, "bmr_solve")
     info = SolveInfo(int(stats.status), int(stats.band_iters), int(stats.block_iters), int(stats.n_replaced),
                      int(stats.n_explicit_qr), np.array(stats.res_rec[:p]), float(stats.time_ms))
     info.precision = precision
     info.res_explicit = np.array(stats.res_explicit[:p])
+    info.n_retained = int(stats.n_retained)
     if precision == "mixed":
         info.n_refine = int(stats.n_refine)
         info.res_true = np.array(stats.res_true[:p])

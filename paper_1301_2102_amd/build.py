@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbmr.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels_spmm.hip", "kernels_band.hip", "kernels_stream.hip", "kernels_colqr.hip", "solver.cpp", "residual_noalloc.hip"]
+SOURCES = ["kernels_spmm.hip", "kernels_band.hip", "kernels_stream.hip", "kernels_colqr.hip", "kernels_ic0.hip", "solver.cpp", "precond.cpp", "residual_noalloc.hip"]
 ARCH = os.environ.get("BMR_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "bmr.h"
 
 namespace bmr {
@@ -118,7 +120,33 @@ struct DevState {
   int qr_b;
   int qr_lcap;                  // first column without a basis vector (p when none)
   int qr_error;                 // a non-finite norm was met
+  // ---- retained removed candidates (BMR_FLAG_RETAIN) ----------------------
+  // A removed candidate that would have been basis vector u_m is kept,
+  // normalised, in slot s of the retained array (n x nb, like the bench),
+  // and the new basis vectors u_{m+1} .. u_{m+2p} take one Gram-Schmidt
+  // step against it.  Each removal takes a bench vector, so at most nb are
+  // ever kept.  While one is in its window the band kernel sends every block
+  // to the column-wise QR, which applies those steps.
+  // ---- accumulated rotations (BMR_FLAG_ACCUMULATE) -------------------------
+  // Qacc[b & 1] holds the p^2 rotations of block b multiplied into one 2p x 2p
+  // matrix (rows of blocks b and b+1), formed by the band kernel of block b+1.
+  int accumulate;
+  double Qacc[2][2 * MAXP][2 * MAXP];
+  int retain;
+  int n_kept;
+  int qr_keep;                  // the current column's candidate is kept in slot qr_keep_slot
+  int qr_keep_slot;
+  int qr_hit;                   // the current column's substitute was projected out of a kept candidate
+  int64_t kept_m[MAXB];
+  // With retained candidates the basis is no longer exactly orthonormal, and
+  // a new block is orthogonalised in the oracle's order (modified
+  // Gram-Schmidt, symmetric coefficients from storage): qr_M[r * MAXP + l]
+  // (r >= l) is the coefficient of u_{(k-1)p+r+1} in the candidate of column l.
+  double qr_M[MAXP * MAXP];
 };
+// Retained candidates need a norm above this fraction of the dependence
+// test's reference norm (2^-26): below it most of their direction is rounding.
+constexpr double RETAIN_FLOOR = 1.0 / 67108864.0;
 
 // Workspace carve-up (offsets into the caller's workspace).  The blocks V, M
 // and the bench hold the storage type of the solve (8 bytes for FP64, 4 for
@@ -127,11 +155,44 @@ struct DevState {
 struct Layout {
   size_t off_state, off_red, off_part, off_hist, off_V, off_M, off_bench;
   size_t off_val32, off_D, off_R;  // BMR_PREC_MIXED only
+  size_t off_Y, off_Z;             // BMR_PRECOND_IC0 only: two n x p blocks for the operator
+  size_t off_ret;                  // BMR_FLAG_RETAIN only: retained candidates, n x nb
   size_t total;
   int n_wg;  // workgroups of pass 1 (partials)
 };
 
-Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision);
+Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision, int precond = 0,
+                  bool retain = false);
+
+// An IC(0) factor in its device buffer (see kernels_ic0.hip): device
+// pointers into the buffer, and the level boundaries on the host (the
+// launches of a level-scheduled solve need them).
+struct Ic0View {
+  int64_t n = 0, nnz_l = 0;
+  int n_levels = 0;
+  std::vector<int> level_ptr;  // host, n_levels + 1: rows level_rows[level_ptr[l] .. level_ptr[l+1]) form level l
+  const int32_t* level_rows = nullptr;
+  const int32_t *lrp = nullptr, *lci = nullptr, *lmap = nullptr, *dmap = nullptr;  // strictly lower part of C
+  const int32_t *urp = nullptr, *uci = nullptr, *upos = nullptr;                   // its transpose
+  double *lval = nullptr, *uval = nullptr, *diag = nullptr;
+  // two-level factors (every row's entries point at rows without entries,
+  // as in a red-black ordering): the coefficients divided by the pivot of
+  // the row they multiply, so that a solve is one gather
+  double *lval_s = nullptr, *uval_s = nullptr;
+  int* fail = nullptr;
+};
+// Reads the header of an IC(0) buffer (synchronously).  0 or a bmr_status error.
+int ic0_view(const void* buf, Ic0View* v);
+hipError_t launch_ic0_factor(const Ic0View& v, const double* mval, int* fail, hipStream_t s);
+// y = C^{-1} rhs (trans = false) or C^{-T} rhs (trans = true), p right-hand
+// sides; rhs may be y.  st: a solver state whose halt flag turns the solve
+// into a no-op, or NULL.
+hipError_t launch_ic0_solve(const Ic0View& v, int p, bool trans, const double* rhs, double* y, const DevState* st,
+                            hipStream_t s);
+// Pass 1 for a preconditioned operator whose product with V_k is already in
+// Z: W = Z - V_{k-1} B_{k-1}^T and the Gram partials, as launch_pass1.
+hipError_t launch_pass1_ident(int p, const double* Z, double* Vbase, size_t slot_elems, const double* bench,
+                              double* part, int n_wg, int64_t n, DevState* st, hipStream_t s);
 // R = B - A X (R may be NULL) and the column norms ||b_i - A x_i|| (host
 // output), with p * n_wg doubles of partial sums in part and p reduced sums in
 // red (device scratch); synchronises the stream.  0 or a bmr_status error.
@@ -150,7 +211,8 @@ template <typename T>
 hipError_t launch_pass1(int p, const bmr_csr_t& A, const T* val, T* Vbase, size_t slot_elems, const T* bench,
                         double* part, int n_wg, DevState* st, hipStream_t s);
 template <typename T>
-hipError_t launch_spmm(int p, const bmr_csr_t& A, const T* val, const T* V, T* W, hipStream_t s);
+hipError_t launch_spmm(int p, const bmr_csr_t& A, const T* val, const T* V, T* W, hipStream_t s,
+                       const DevState* st = nullptr);  // st: halt flag makes it a no-op
 hipError_t launch_residual(int p, const bmr_csr_t& A, const double* B, const double* X, double* R,
                            double* part, int n_wg, hipStream_t s);
 hipError_t launch_reduce(const double* part, int n_wg, int n_ent, double* red, DevState* st, int check_halt,
@@ -177,9 +239,10 @@ hipError_t launch_bench_init(T* bench, int64_t n, int nb, uint64_t seed, hipStre
 // reference norms ||A u_j|| from the state), and at the end B_k := qr_R, the
 // column cap and the counters go to the state and the device loop resumes.
 enum { QR_SETUP = 0, QR_LOOP = 1 };
+// ret: the retained candidates (n x nb, storage type T), or NULL when none are kept.
 template <typename T>
 hipError_t launch_colqr(int p, int mode, T* D, const T* Vk, T* bench, int nb, int64_t n, double* part, int n_wg,
-                        DevState* st, hipStream_t s);
+                        DevState* st, hipStream_t s, T* ret = nullptr);
 int colqr_grid(int64_t n);
 // Column kernels of the set-up norms, FP64 arithmetic.
 //   coldots: part[wg * (m+1) + r] = sum_i X[i*ldx + r] * Y[i*ldy + yc] (r < m), last = sum Y^2

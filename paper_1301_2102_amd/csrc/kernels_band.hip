@@ -162,6 +162,7 @@ struct BandShared {
   double Wg[P * MAXB], Vg[P * MAXB];  // W^T g_b and V_k^T g_b (bench inner products)
   double rot[2][P][P][2];  // rotations of blocks k-2 and k-1
   double nrot[P][P][2];    // rotations of block k
+  double Qb[2][2 * P][2 * P + 1];  // accumulated rotations of blocks k-2 and k-1 (accumulating mode)
   double col[P][4 * P + 1];  // column l of H-bar, rows of blocks k-2 .. k+1
   double s2[P][2 * P + 1];   // column q of the S-hat window (p live + p new rows)
 };
@@ -171,6 +172,7 @@ struct BandCtl {
   int64_t k, j0, max_iter, hist_cap;
   int halt, lcap, cap_status, taken;
   double tol, tau_fb;
+  bool force_qr;  // a retained candidate still applies to the new block's basis vectors
 };
 
 // Every global input of the band kernel, loaded into registers before the
@@ -201,6 +203,10 @@ __device__ __attribute__((always_inline)) inline void load_band(int mode, int nb
   c.taken = st->taken;
   c.tol = st->tol;
   c.tau_fb = st->tau_fb;
+  // the new block holds u_{kp+1} .. u_{kp+p}; a candidate kept in place of
+  // u_m applies to u_{m+1} .. u_{m+2p}
+  c.force_qr = false;
+  for (int q = 0; q < st->n_kept; ++q) c.force_qr |= st->kept_m[q] + 2 * P >= c.k * P + 1;
 #pragma unroll
   for (int x = 0; x < BL::N; ++x) {
     const int e = tid + 64 * x;
@@ -632,6 +638,76 @@ __device__ void prev_rotations(BandShared<P>& sh) {
 // Phase B: Givens QR of the p new columns of H-bar, S-hat window, residuals,
 // stopping test, coefficients of the search directions and of the X update.
 // Runs on the first wavefront after the rotations of the previous blocks.
+// The same rows in the accumulating form (Section 4's remark on keeping the
+// action of a block of reflectors as one matrix): the p^2 rotations of block
+// k-1 are multiplied into one orthogonal 2p x 2p matrix Q_{k-1} over the rows
+// of blocks k-1 and k (lane q forms column q; it is also kept in the state
+// for the next block), and the new block's columns take Q_{k-2} (formed by
+// the previous block's kernel) and Q_{k-1} as matrix products.  Q_{k-2}
+// also holds the rotations of block k-2's first columns, which the
+// sequential form skips for the columns to their right: they act on rows
+// that are still zero there, so only the rounding changes.
+template <int P>
+__device__ void prev_rotations_acc(BandShared<P>& sh, DevState* __restrict__ st, int64_t k) {
+  const int lane = threadIdx.x & 63;
+  for (int e = lane; e < 3 * P * P; e += 64) {
+    const int l = e / (3 * P), r = e % (3 * P);
+    double v = 0.0;
+    if (r >= P && r < 2 * P) v = (r - P >= l) ? sh.Bp[l][r - P] : 0.0;
+    if (r >= 2 * P) v = sh.Ak[r - 2 * P][l];
+    sh.col[l][r] = v;
+  }
+  const bool have0 = k - 2 >= 1, have1 = k - 1 >= 1;
+  if (lane < 2 * P) {
+    const int q = lane;
+    double qc[2 * P];
+#pragma unroll
+    for (int r = 0; r < 2 * P; ++r) qc[r] = r == q ? 1.0 : 0.0;
+    if (have1) {
+#pragma unroll 1
+      for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int t = 0; t < P; ++t) rotate(sh.rot[1][i][t][0], sh.rot[1][i][t][1], qc[i], qc[i + t + 1]);
+    }
+    double (*Qk1)[2 * MAXP] = st->Qacc[(k + 1) & 1];  // slot of block k-1
+    const double (*Qk2)[2 * MAXP] = st->Qacc[k & 1];  // slot of block k-2
+#pragma unroll
+    for (int r = 0; r < 2 * P; ++r) {
+      sh.Qb[1][r][q] = qc[r];
+      Qk1[r][q] = qc[r];
+      sh.Qb[0][r][q] = have0 ? Qk2[r][q] : (r == q ? 1.0 : 0.0);
+    }
+  }
+  wave_sync();
+  // rows [0, 2p) by Q_{k-2}, then rows [p, 3p) by Q_{k-1}; each lane forms
+  // up to NO outputs in registers before any is written back
+  constexpr int NO = (2 * P * P + 63) / 64;
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    if (w == 0 ? !have0 : !have1) continue;
+    const int off = w * P;
+    double o[NO];
+#pragma unroll
+    for (int x = 0; x < NO; ++x) {
+      const int e = lane + 64 * x;
+      double a = 0.0;
+      if (e < 2 * P * P) {
+        const int l = e / (2 * P), r = e % (2 * P);
+#pragma unroll
+        for (int t = 0; t < 2 * P; ++t) a = fma(sh.Qb[w][r][t], sh.col[l][off + t], a);
+      }
+      o[x] = a;
+    }
+    wave_sync();
+#pragma unroll
+    for (int x = 0; x < NO; ++x) {
+      const int e = lane + 64 * x;
+      if (e < 2 * P * P) sh.col[e / (2 * P)][off + e % (2 * P)] = o[x];
+    }
+    wave_sync();
+  }
+}
+
 template <int P>
 __device__ void phase_b(const BandCtl ctl, DevState* __restrict__ st, double* __restrict__ hist, BandShared<P>& sh) {
   const int tid = threadIdx.x;
@@ -848,7 +924,7 @@ __global__ __launch_bounds__(128) void k_band(int mode, int nb, const double* __
   bool ok = true;
   if (first) {
     if (mode == 0) {
-      ok = phase_a<P>(nb, ctl.taken, ctl.tau_fb, st, sh);
+      ok = !ctl.force_qr && phase_a<P>(nb, ctl.taken, ctl.tau_fb, st, sh);
       if (!ok && threadIdx.x == 0) {
         for (int e = 0; e < P * P; ++e) st->Ak[(e / P) * MAXP + (e % P)] = sh.Ak[e / P][e % P];
         for (int c = 0; c < P; ++c) st->araw[c] = sh.araw[c];
@@ -864,6 +940,8 @@ __global__ __launch_bounds__(128) void k_band(int mode, int nb, const double* __
       }
       for (int e = threadIdx.x; e < MAXB * MAXP; e += 64) st->bcoef[e] = 0.0;
     }
+  } else if (st->accumulate) {
+    prev_rotations_acc<P>(sh, st, st->k);
   } else {
     prev_rotations<P>(sh);
   }

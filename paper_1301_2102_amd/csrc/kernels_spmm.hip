@@ -398,11 +398,14 @@ __device__ inline T group_sum(T x) {
   return x;
 }
 
-template <int P, typename T>
+// IDENT: the operator's product with V_k was formed beforehand (the
+// preconditioned operator) and is read row by row from Z instead of gathered.
+template <int P, typename T, bool IDENT = false>
 __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                               const T* __restrict__ va, int64_t n, T* __restrict__ Vbase,
                                               size_t slot, const T* __restrict__ bench,
-                                              double* __restrict__ part, int n_wg, DevState* __restrict__ st) {
+                                              double* __restrict__ part, int n_wg, DevState* __restrict__ st,
+                                              const T* __restrict__ Z = nullptr) {
   if (st->halt) return;
   using LN = Lanes<P>;
   using Ops = TypeOps<T>;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   int64_t r0, r1;
   row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
   RowPipe<LPR, RPG, T> pipe;
-  pipe.start(rp, ci, va, r0 + wave * RPW + grp, r1, c);
+  if constexpr (!IDENT) pipe.start(rp, ci, va, r0 + wave * RPW + grp, r1, c);
 
   for (int64_t base = r0; base < r1; base += RPG) {
     asm volatile("" ::: "memory");
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
     // pipeline); its own V_k row is loaded with the gathered rows.
     T v[CPL], w[CPL], vpo[CPL], vp[LN::ROW ? P : 1], g[LN::ROW ? MAXB : 1], gb = T(0);
     auto loads = [&]() {
-      pipe.load_ahead(rp, row, r1);
+      if constexpr (!IDENT) pipe.load_ahead(rp, row, r1);
       if constexpr (LN::ROW) {
 #pragma unroll
         for (int r = 0; r < P; ++r) vp[r] = valid ? Vp[row * P + r] : T(0);
@@ -484,9 +487,15 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
     };
     T a[CPL];
     const T* own = (valid && c0 < P) ? V + row * P + c0 : nullptr;
-    gather_se<P, LPR, CPL, true, RowPipe<LPR, RPG, T>::PIPE>(ci, va, V, pipe.s_cur, pipe.e_cur, c, a, own, v,
-                                                             &pipe.lead, pipe.s_nx, pipe.e_nx, loads);
-    pipe.advance();
+    if constexpr (IDENT) {
+      loads();
+      load_own<CPL>(own, v);
+      load_own<CPL>((valid && c0 < P) ? Z + row * P + c0 : nullptr, a);
+    } else {
+      gather_se<P, LPR, CPL, true, RowPipe<LPR, RPG, T>::PIPE>(ci, va, V, pipe.s_cur, pipe.e_cur, c, a, own, v,
+                                                               &pipe.lead, pipe.s_nx, pipe.e_nx, loads);
+      pipe.advance();
+    }
     if constexpr (LN::ROW) {
       // the lane owns the whole row: everything stays in registers
 #pragma unroll
@@ -650,7 +659,8 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
 template <int P, typename T>
 __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const T* __restrict__ va, int64_t n, const T* __restrict__ V,
-                                             T* __restrict__ W, int n_wg) {
+                                             T* __restrict__ W, int n_wg, const DevState* __restrict__ st) {
+  if (st && st->halt) return;
   using LN = Lanes<P>;
   constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -803,9 +813,11 @@ hipError_t launch_pass1(int p, const bmr_csr_t& A, const T* val, T* Vbase, size_
 }
 
 template <typename T>
-hipError_t launch_spmm(int p, const bmr_csr_t& A, const T* val, const T* V, T* W, hipStream_t s) {
+hipError_t launch_spmm(int p, const bmr_csr_t& A, const T* val, const T* V, T* W, hipStream_t s,
+                       const DevState* st) {
   const int n_wg = spmm_grid(A.n, p);
-#define L2(P) hipLaunchKernelGGL((k_spmm<P, T>), dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, val, A.n, V, W, n_wg)
+#define L2(P) \
+  hipLaunchKernelGGL((k_spmm<P, T>), dim3(n_wg), dim3(WG), 0, s, A.row_ptr, A.col_idx, val, A.n, V, W, n_wg, st)
   BMR_DISPATCH_P(p, L2)
 #undef L2
   return hipGetLastError();
@@ -815,8 +827,20 @@ template hipError_t launch_pass1<double>(int, const bmr_csr_t&, const double*, d
                                          double*, int, DevState*, hipStream_t);
 template hipError_t launch_pass1<float>(int, const bmr_csr_t&, const float*, float*, size_t, const float*, double*,
                                         int, DevState*, hipStream_t);
-template hipError_t launch_spmm<double>(int, const bmr_csr_t&, const double*, const double*, double*, hipStream_t);
-template hipError_t launch_spmm<float>(int, const bmr_csr_t&, const float*, const float*, float*, hipStream_t);
+template hipError_t launch_spmm<double>(int, const bmr_csr_t&, const double*, const double*, double*, hipStream_t,
+                                        const DevState*);
+template hipError_t launch_spmm<float>(int, const bmr_csr_t&, const float*, const float*, float*, hipStream_t,
+                                       const DevState*);
+
+hipError_t launch_pass1_ident(int p, const double* Z, double* Vbase, size_t slot, const double* bench, double* part,
+                              int n_wg, int64_t n, DevState* st, hipStream_t s) {
+#define L4(P)                                                                                                   \
+  hipLaunchKernelGGL((k_pass1<P, double, true>), dim3(n_wg), dim3(WG), 0, s, (const int32_t*)nullptr,          \
+                     (const int32_t*)nullptr, (const double*)nullptr, n, Vbase, slot, bench, part, n_wg, st, Z)
+  BMR_DISPATCH_P(p, L4)
+#undef L4
+  return hipGetLastError();
+}
 
 hipError_t launch_residual(int p, const bmr_csr_t& A, const double* Bm, const double* X, double* R, double* part,
                            int n_wg, hipStream_t s) {

@@ -72,6 +72,11 @@ struct Run {
   T *V, *M, *bench;
   size_t slot;
   std::vector<double> hpart;
+  // split preconditioning (FP64 only): the operator is C^{-1} A C^{-T},
+  // formed block by block in Y (C^{-T} V_k) and Z (A Y, then C^{-1} in place)
+  const Ic0View* pc = nullptr;
+  double *Y = nullptr, *Z = nullptr;
+  T* ret = nullptr;  // retained removed candidates (n x nb), or NULL
 
   T* Vslot(int64_t k) { return V + (size_t)(k % ring_len(p)) * slot; }
 
@@ -92,7 +97,7 @@ struct Run {
   }
   // Column-wise QR of the block D on the device (launches only).
   int colqr(int mode, T* D, const T* Vk) {
-    HIP_TRY(launch_colqr<T>(p, mode, D, Vk, bench, nb, n, part, colqr_grid(n), st, s));
+    HIP_TRY(launch_colqr<T>(p, mode, D, Vk, bench, nb, n, part, colqr_grid(n), st, s, ret));
     return 0;
   }
 };
@@ -105,7 +110,8 @@ struct Run {
 
 }  // namespace
 
-Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision) {
+Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision, int precond,
+                  bool retain) {
   const bool mixed = precision == BMR_PREC_MIXED;
   const size_t esz = mixed ? sizeof(float) : sizeof(double);
   Layout L{};
@@ -137,6 +143,16 @@ Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int p
     L.off_R = off;
     off = align256(off + sizeof(double) * (size_t)n * p);
   }
+  if (retain) {
+    L.off_ret = off;
+    off = align256(off + esz * (size_t)n * nb);
+  }
+  if (precond == BMR_PRECOND_IC0) {
+    L.off_Y = off;
+    off = align256(off + sizeof(double) * (size_t)n * p);
+    L.off_Z = off;
+    off = align256(off + sizeof(double) * (size_t)n * p);
+  }
   L.total = off;
   return L;
 }
@@ -165,7 +181,8 @@ bool opts_valid(const bmr_opts_t& o) {
   return o.tol > 0.0 && isfinite(o.tol) && o.max_iter >= 1 && o.gamma >= 0.0 && isfinite(o.gamma) &&
          o.n_bench >= 0 && o.n_bench <= BMR_MAX_BENCH && o.hist_cap >= 0 && o.poll_every >= 0 &&
          (o.precision == BMR_PREC_FP64 || o.precision == BMR_PREC_MIXED) &&
-         (o.precision == BMR_PREC_FP64 || (o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_refine >= 1));
+         (o.precision == BMR_PREC_FP64 || (o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_refine >= 1)) &&
+         (o.precond == BMR_PRECOND_NONE || (o.precond == BMR_PRECOND_IC0 && o.precision == BMR_PREC_FP64));
 }
 
 bool csr_valid(const bmr_csr_t* A) {
@@ -198,10 +215,11 @@ struct CoreParams {
   int poll_every;
   bool prof;
   const double* beta_stop;  // per-column scale of the stopping test, or NULL for ||b_i||
+  bool accumulate = false;  // apply the previous blocks' rotations as accumulated matrices
 };
 struct CoreOut {
   int64_t j = 0, k = 0;
-  int n_replaced = 0, n_explicit = 0;
+  int n_replaced = 0, n_explicit = 0, n_kept = 0;
   double rho[MAXP] = {};
   double bnorm[MAXP] = {};  // ||b_i|| of the right-hand side solved
   double tk[4] = {0, 0, 0, 0};  // summed kernel times over n_prof block iterations
@@ -237,6 +255,8 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   hs->tau_fb = o.tau_fb;
   hs->lcap = p;
   hs->k = 1;
+  hs->retain = r.ret != nullptr;
+  hs->accumulate = o.accumulate;
 
   double c[MAXP + 1];
   double bnorm[MAXP];
@@ -256,6 +276,7 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     out.k = kblocks;
     out.n_replaced = hs->n_replaced;
     out.n_explicit = hs->n_explicit;
+    out.n_kept = hs->n_kept;
     for (int i = 0; i < MAXP; ++i) out.rho[i] = (i < p && rho) ? rho[i] : 0.0;
   };
   // initial QR of F_0 = B into V_1 (slot 1): copy (rounded to T), then
@@ -311,7 +332,7 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     }
   } evg{ev};
   int batch = o.poll_every;
-  if (batch <= 0) batch = ((double)n * p < 2e6) ? 32 : 16;
+  if (batch <= 0) batch = r.pc ? 4 : ((double)n * p < 2e6) ? 32 : 16;
   const bool prof = o.prof;
   if (prof) batch = 1;
   hipEvent_t pev[2][5];
@@ -352,7 +373,23 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   auto enq = [&](int slot) -> int {
     for (int q = 0; q < batch; ++q, ++kq) {
       if (prof) HIP_TRY(hipEventRecord(pev[slot][0], r.s));
-      HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
+      if constexpr (sizeof(T) == sizeof(double)) {
+        if (r.pc) {  // W = C^{-1} A C^{-T} V_k, then pass 1 on the formed product
+          const double* Vk = (const double*)r.Vslot(kq);
+          HIP_TRY(launch_ic0_solve(*r.pc, p, true, Vk, r.Y, r.st, r.s));
+          HIP_TRY(launch_spmm<double>(p, *r.A, r.A->val, r.Y, r.Z, r.s, r.st));
+          // a two-level factor solves out of place in one launch (Z -> Y),
+          // others level by level in place
+          double* F = r.pc->n_levels == 2 ? r.Y : r.Z;
+          HIP_TRY(launch_ic0_solve(*r.pc, p, false, r.Z, F, r.st, r.s));
+          HIP_TRY(launch_pass1_ident(p, F, (double*)r.V, r.slot, (const double*)r.bench, r.part, r.n_wg, n,
+                                     r.st, r.s));
+        } else {
+          HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
+        }
+      } else {
+        HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
+      }
       if (prof) HIP_TRY(hipEventRecord(pev[slot][1], r.s));
       HIP_TRY(launch_reduce(r.part, r.n_wg, n_entries(r.p, r.nb), r.red, r.st, 1, r.s));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][2], r.s));
@@ -434,6 +471,7 @@ void bind(Run<T>& r, const bmr_csr_t* A, const T* val, int p, int nb, hipStream_
   r.M = (T*)(ws + L.off_M);
   r.bench = (T*)(ws + L.off_bench);
   r.slot = slot_elems(A->n, p);
+  r.ret = L.off_ret ? (T*)(ws + L.off_ret) : nullptr;
 }
 
 void fill_stats(bmr_stats_t* stats, int status, int p, const CoreOut& o) {
@@ -444,28 +482,51 @@ void fill_stats(bmr_stats_t* stats, int status, int p, const CoreOut& o) {
   stats->band_iters = o.j;
   stats->block_iters = o.k;
   stats->n_explicit_qr = o.n_explicit;
+  stats->n_retained = o.n_kept;
   stats->p = p;
   for (int i = 0; i < BMR_MAX_P; ++i) stats->res_rec[i] = i < p ? o.rho[i] : 0.0;
   for (int q = 0; q < 4; ++q) stats->t_kernel_ms[q] = o.n_prof ? o.tk[q] / o.n_prof : 0.0;
   stats->n_profiled = o.n_prof;
 }
 
+// pc: with an IC(0) factor C, block MINRES runs on C^{-1} A C^{-T} with
+// right-hand sides C^{-1} B (formed in Y before the iteration takes Y over),
+// and X = C^{-T} X-hat at the end; the stopping test and res_rec refer to
+// the preconditioned residual, res_explicit to B - A X.
 int solve_fp64(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_opts_t& o, char* ws,
-               const Layout& L, hipStream_t s, bmr_stats_t* stats, double* res_hist) {
+               const Layout& L, hipStream_t s, bmr_stats_t* stats, double* res_hist, const Ic0View* pc = nullptr) {
   Run<double> r{};
   bind(r, A, A->val, p, o.n_bench, s, ws, L);
+  const double* rhs = B;
+  if (pc) {
+    r.pc = pc;
+    r.Y = (double*)(ws + L.off_Y);
+    r.Z = (double*)(ws + L.off_Z);
+    HIP_TRY(launch_ic0_solve(*pc, p, false, B, r.Y, nullptr, s));
+    rhs = r.Y;
+  }
   CoreParams cp{o.tol, o.gamma, TAU_FB, o.max_iter, o.hist_cap, o.seed, o.poll_every,
-                (o.flags & BMR_FLAG_PROFILE) != 0, nullptr};
+                (o.flags & BMR_FLAG_PROFILE) != 0, nullptr, (o.flags & BMR_FLAG_ACCUMULATE) != 0};
   CoreOut out;
-  const int status = solve_core<double>(r, B, X, cp, out, res_hist);
+  const int status = solve_core<double>(r, rhs, X, cp, out, res_hist);
   if (status < 0) return status;
+  double bnorm[MAXP];
+  for (int i = 0; i < p; ++i) bnorm[i] = out.bnorm[i];
+  if (pc) {  // X = C^{-T} X-hat in place; the explicit residual is relative to ||b_i||
+    HIP_TRY(launch_ic0_solve(*pc, p, true, X, X, nullptr, s));
+    double c[MAXP + 1];
+    for (int i = 0; i < p; ++i) {
+      TRY(r.coldots(B, p, i, (const double*)nullptr, 0, 0, c));
+      bnorm[i] = sqrt(c[0]);
+    }
+  }
   // the explicit residual of the result, reported beside the recurrence
   // values (Algorithm 7.1's output)
   double rn[MAXP];
   TRY(residual_norms(A, B, X, p, nullptr, r.part, L.n_wg, r.red, s, rn));
   fill_stats(stats, status, p, out);
   if (stats)
-    for (int i = 0; i < p; ++i) stats->res_explicit[i] = out.bnorm[i] > 0 ? rn[i] / out.bnorm[i] : 0.0;
+    for (int i = 0; i < p; ++i) stats->res_explicit[i] = bnorm[i] > 0 ? rn[i] / bnorm[i] : 0.0;
   return status;
 }
 
@@ -520,7 +581,7 @@ int solve_mixed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr
     prev_worst = worst;
     for (int i = 0; i < p; ++i) stop[i] = std::max(rn[i], 0.5 * o.tol * beta[i] / o.inner_tol);
     CoreParams cp{o.inner_tol, std::max(o.gamma, GAMMA_F32), TAU_FB_F32, o.max_iter - tot.j, 0, o.seed,
-                  o.poll_every, (o.flags & BMR_FLAG_PROFILE) != 0, stop};
+                  o.poll_every, (o.flags & BMR_FLAG_PROFILE) != 0, stop, (o.flags & BMR_FLAG_ACCUMULATE) != 0};
     CoreOut out;
     const int st = solve_core<float>(r, R, D, cp, out, nullptr);
     if (st < 0) return st;
@@ -562,6 +623,7 @@ const char* bmr_status_string(int status) {
     case BMR_HIP_ERROR: return "HIP runtime error";
     case BMR_NONFINITE: return "non-finite value";
     case BMR_SINGULAR_R: return "singular band QR factor";
+    case BMR_IC0_BREAKDOWN: return "incomplete Cholesky factorisation broke down";
     default: return "unknown status";
   }
 }
@@ -587,7 +649,8 @@ int bmr_workspace_bytes(int64_t n, int64_t nnz, int p, const bmr_opts_t* opts, s
   bmr_default_opts(&o);
   if (opts) o = *opts;
   if (!bytes || n < 1 || nnz < 0 || p < 1 || p > BMR_MAX_P || !opts_valid(o)) return BMR_INVALID_ARG;
-  *bytes = layout_for(n, nnz, p, o.n_bench, o.hist_cap, o.precision).total;
+  *bytes = layout_for(n, nnz, p, o.n_bench, o.hist_cap, o.precision, o.precond, (o.flags & BMR_FLAG_RETAIN) != 0)
+               .total;
   return BMR_CONVERGED;
 }
 
@@ -597,8 +660,10 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
   bmr_default_opts(&o);
   if (opts) o = *opts;
   if (!csr_valid(A) || !B || !X || !workspace || p < 1 || p > BMR_MAX_P || !opts_valid(o)) return BMR_INVALID_ARG;
+  if (o.precond != BMR_PRECOND_NONE) return BMR_INVALID_ARG;  // the factor comes with bmr_solve_ic0
   if (((uintptr_t)workspace) % 256 != 0 || !aligned16(B) || !aligned16(X)) return BMR_INVALID_ARG;
-  const Layout L = layout_for(A->n, A->nnz, p, o.n_bench, o.hist_cap, o.precision);
+  const Layout L = layout_for(A->n, A->nnz, p, o.n_bench, o.hist_cap, o.precision, BMR_PRECOND_NONE,
+                              (o.flags & BMR_FLAG_RETAIN) != 0);
   if (workspace_bytes < L.total) return BMR_WORKSPACE_TOO_SMALL;
   hipEvent_t t0, t1;
   if (hipEventCreate(&t0) != hipSuccess) return BMR_HIP_ERROR;
@@ -620,6 +685,49 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
       stats->p = p;
     }
     stats->precision = o.precision;
+    stats->time_ms = ms;
+  }
+  return status;
+}
+
+int bmr_solve_ic0(const bmr_csr_t* A, const void* ic0, const double* B, double* X, int p, const bmr_opts_t* opts,
+                  void* workspace, size_t workspace_bytes, hipStream_t stream, bmr_stats_t* stats,
+                  double* res_hist) {
+  bmr_opts_t o;
+  bmr_default_opts(&o);
+  if (opts) o = *opts;
+  o.precond = BMR_PRECOND_IC0;
+  if (!csr_valid(A) || !ic0 || !B || !X || !workspace || p < 1 || p > BMR_MAX_P || !opts_valid(o))
+    return BMR_INVALID_ARG;
+  if (((uintptr_t)workspace) % 256 != 0 || !aligned16(B) || !aligned16(X) || B == X) return BMR_INVALID_ARG;
+  const Layout L = layout_for(A->n, A->nnz, p, o.n_bench, o.hist_cap, o.precision, o.precond,
+                              (o.flags & BMR_FLAG_RETAIN) != 0);
+  if (workspace_bytes < L.total) return BMR_WORKSPACE_TOO_SMALL;
+  Ic0View v;
+  const int e = ic0_view(ic0, &v);
+  if (e) return e;
+  if (v.n != A->n) return BMR_INVALID_ARG;
+  hipEvent_t t0, t1;
+  if (hipEventCreate(&t0) != hipSuccess) return BMR_HIP_ERROR;
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return BMR_HIP_ERROR;
+  }
+  (void)hipEventRecord(t0, stream);
+  const int status = solve_fp64(A, B, X, p, o, (char*)workspace, L, stream, stats, res_hist, &v);
+  (void)hipEventRecord(t1, stream);
+  (void)hipEventSynchronize(t1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, t0, t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (stats) {
+    if (status < 0) {
+      memset(stats, 0, sizeof(*stats));
+      stats->status = status;
+      stats->p = p;
+    }
+    stats->precision = BMR_PREC_FP64;
     stats->time_ms = ms;
   }
   return status;

@@ -43,7 +43,7 @@ def test_default_opts(lib):
     lib.bmr_default_opts(ctypes.byref(o))
     assert (o.tol, o.max_iter, o.gamma, o.n_bench, o.seed, o.hist_cap, o.flags) == (1e-8, 10000, 1e-10, 2, 0, 0, 0)
     assert (o.precision, o.inner_tol, o.max_refine) == (bmr.PREC_FP64, 1e-6, 30)
-    assert ctypes.sizeof(bmr._Opts) == 72 and ctypes.sizeof(bmr._Stats) == 472  # sizeof in C
+    assert ctypes.sizeof(bmr._Opts) == 72 and ctypes.sizeof(bmr._Stats) == 480  # sizeof in C
 
 
 def test_workspace_bytes(lib):
@@ -126,3 +126,31 @@ def test_no_cpu_fallback_in_product_path():
             if f.endswith((".py", ".cpp", ".hip", ".hpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_ic0_and_precond_arguments_rejected_on_host(lib):
+    out = ctypes.c_size_t()
+    assert lib.bmr_ic0_bytes(0, 0, ctypes.byref(out)) == bmr.INVALID_ARG
+    assert lib.bmr_ic0_bytes(10, -1, ctypes.byref(out)) == bmr.INVALID_ARG
+    assert lib.bmr_ic0_bytes(10, 28, ctypes.byref(out)) == bmr.CONVERGED and out.value > 10 * 8
+    assert lib.bmr_ic0_factor(None, 256, 1 << 20, None) == bmr.INVALID_ARG
+    A = bmr._Csr(10, 28, 256, 256, 256)
+    assert lib.bmr_ic0_factor(ctypes.byref(A), 300, 1 << 20, None) == bmr.INVALID_ARG  # unaligned buffer
+    assert lib.bmr_ic0_apply(None, 256, 256, 2, 0, None) == bmr.INVALID_ARG
+    assert lib.bmr_ic0_apply(256, 256, 256, 17, 0, None) == bmr.INVALID_ARG
+    o = bmr._Opts()
+    lib.bmr_default_opts(ctypes.byref(o))
+    assert o.precond == bmr.PRECOND_NONE
+    # bmr_solve takes no preconditioner; bmr_solve_ic0 needs its object
+    o.precond = bmr.PRECOND_IC0
+    assert lib.bmr_solve(ctypes.byref(A), 256, 512, 2, ctypes.byref(o), 256, 1 << 30, None, None, None) == \
+        bmr.INVALID_ARG
+    assert lib.bmr_solve_ic0(ctypes.byref(A), None, 256, 512, 2, None, 256, 1 << 30, None, None, None) == \
+        bmr.INVALID_ARG
+    o.precond = 7
+    assert lib.bmr_workspace_bytes(10, 28, 2, ctypes.byref(o), ctypes.byref(out)) == bmr.INVALID_ARG
+    # the preconditioned workspace holds two more n x p blocks
+    n, p = 4096, 4
+    plain = bmr.workspace_bytes(n, p)
+    pre = bmr.workspace_bytes(n, p, precond="ic0")
+    assert pre >= plain + 2 * n * p * 8

@@ -13,6 +13,8 @@ from .gen import (  # noqa: F401
     rhs_stress,
     rhs_e1_ae1,
     rhs_near_copy,
+    permuted,
+    redblack_order,
     rhs_near_e1_ae1,
     diag_positions,
     with_diagonal_shift,

@@ -114,6 +114,30 @@ def random_symmetric(n: int, draws: int = 13, seed: int = 0, diag_range: float =
     return Csr(n, indptr.astype(np.int32), c.astype(np.int32), v.astype(np.float64))
 
 
+def permuted(A: Csr, perm: np.ndarray) -> Csr:
+    """P A P^T for the row order ``perm`` (row i of the result is row perm[i]
+    of A), columns sorted: the same operator with the unknowns renumbered."""
+    import scipy.sparse as sp
+    n = A.n
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), np.asarray(perm))), shape=(n, n))
+    B = (P @ A.to_scipy() @ P.T).tocsr()
+    B.sort_indices()
+    return Csr(n, B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64))
+
+
+def redblack_order(dims) -> np.ndarray:
+    """Red-black (two-colour) ordering of a regular grid in lexicographic
+    x-fastest numbering: every point with an even coordinate sum first, in
+    lexicographic order, then the others.  Stencil neighbours have opposite
+    colours, so the lower triangle of the reordered Laplacian couples only
+    black rows to red ones."""
+    dims = tuple(int(d) for d in dims)
+    idx = np.indices(dims[::-1]).reshape(len(dims), -1)  # (z, y, x) or (y, x), lexicographic
+    parity = idx.sum(axis=0) % 2
+    lex = np.arange(int(np.prod(dims)))
+    return np.concatenate([lex[parity == 0], lex[parity == 1]])
+
+
 def rhs_normal(n: int, p: int, seed: int = 0) -> np.ndarray:
     """(n, p) block of independent N(0,1) columns, C-contiguous (row-interleaved)."""
     rng = np.random.default_rng(seed)
