@@ -193,6 +193,15 @@ hipError_t launch_ic0_solve(const Ic0View& v, int p, bool trans, const double* r
 // Z: W = Z - V_{k-1} B_{k-1}^T and the Gram partials, as launch_pass1.
 hipError_t launch_pass1_ident(int p, const double* Z, double* Vbase, size_t slot_elems, const double* bench,
                               double* part, int n_wg, int64_t n, DevState* st, hipStream_t s);
+// y = (rhs - T rhs) / diag for the scaled strictly triangular part T of a
+// two-level IC(0) factor: one whole triangular solve (rhs must not be y).
+hipError_t launch_trisolve2(int p, const int32_t* rp, const int32_t* ci, const double* va, const double* diag,
+                            int64_t n, const double* rhs, double* y, const DevState* st, hipStream_t s);
+// Pass 1 on C^{-1} Z for a two-level IC(0) factor, the forward solve done on
+// the fly from the factor's scaled strictly lower part (lrp, lci, lval_s).
+hipError_t launch_pass1_tri(int p, const int32_t* lrp, const int32_t* lci, const double* lval_s, const double* diag,
+                            const double* Z, double* Vbase, size_t slot_elems, const double* bench, double* part,
+                            int n_wg, int64_t n, DevState* st, hipStream_t s);
 // R = B - A X (R may be NULL) and the column norms ||b_i - A x_i|| (host
 // output), with p * n_wg doubles of partial sums in part and p reduced sums in
 // red (device scratch); synchronises the stream.  0 or a bmr_status error.

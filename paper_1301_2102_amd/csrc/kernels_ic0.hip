@@ -130,39 +130,6 @@ __global__ __launch_bounds__(WG) void k_trsv_level(const int32_t* __restrict__ r
     if (c0 + k < P) y[i * P + c0 + k] = (rhs[i * P + c0 + k] - acc[k]) / d;
 }
 
-// A whole triangular solve of a two-level factor in one launch: every row
-// with entries refers only to rows without any (whose solution is rhs / d),
-// so with the coefficients pre-divided by those pivots
-//     y_i = (rhs_i - sum_{e in row i} va_s[e] rhs_{col e}) / diag_i
-// for all rows at once.  rhs must not be y.
-template <int P>
-__global__ __launch_bounds__(WG) void k_trsv2(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                              const double* __restrict__ va_s, const double* __restrict__ diag,
-                                              int64_t n, const double* __restrict__ rhs, double* __restrict__ y,
-                                              const DevState* __restrict__ st) {
-  if (st && st->halt) return;
-  using S = TrsvShape<P>;
-  constexpr int CPL = S::CPL, LPR = S::LPR;
-  const int64_t i = (int64_t)blockIdx.x * S::RPB + threadIdx.x / LPR;
-  const int c0 = (threadIdx.x % LPR) * CPL;
-  if (i >= n || c0 >= P) return;
-  double acc[CPL];
-#pragma unroll
-  for (int k = 0; k < CPL; ++k) acc[k] = 0.0;
-  const int s = rp[i], e = rp[i + 1];
-  for (int q = s; q < e; ++q) {
-    const int64_t j = ci[q];
-    const double v = va_s[q];
-#pragma unroll
-    for (int k = 0; k < CPL; ++k)
-      if (c0 + k < P) acc[k] = fma(v, rhs[j * P + c0 + k], acc[k]);
-  }
-  const double d = diag[i];
-#pragma unroll
-  for (int k = 0; k < CPL; ++k)
-    if (c0 + k < P) y[i * P + c0 + k] = (rhs[i * P + c0 + k] - acc[k]) / d;
-}
-
 }  // namespace
 
 hipError_t launch_ic0_factor(const Ic0View& v, const double* mval, int* fail, hipStream_t s) {
@@ -183,35 +150,9 @@ hipError_t launch_ic0_factor(const Ic0View& v, const double* mval, int* fail, hi
 
 hipError_t launch_ic0_solve(const Ic0View& v, int p, bool trans, const double* rhs, double* y, const DevState* st,
                             hipStream_t s) {
-  if (v.n_levels == 2 && rhs != y) {  // one launch (two-level factor, out of place)
-    const int32_t* rp = trans ? v.urp : v.lrp;
-    const int32_t* ci = trans ? v.uci : v.lci;
-    const double* va = trans ? v.uval_s : v.lval_s;
-#define L2L(P)                                                                                                  \
-  hipLaunchKernelGGL(k_trsv2<P>, dim3((int)((v.n + TrsvShape<P>::RPB - 1) / TrsvShape<P>::RPB)), dim3(WG), 0, s, \
-                     rp, ci, va, (const double*)v.diag, v.n, rhs, y, st)
-    switch (p) {
-      case 1: L2L(1); break;
-      case 2: L2L(2); break;
-      case 3: L2L(3); break;
-      case 4: L2L(4); break;
-      case 5: L2L(5); break;
-      case 6: L2L(6); break;
-      case 7: L2L(7); break;
-      case 8: L2L(8); break;
-      case 9: L2L(9); break;
-      case 10: L2L(10); break;
-      case 11: L2L(11); break;
-      case 12: L2L(12); break;
-      case 13: L2L(13); break;
-      case 14: L2L(14); break;
-      case 15: L2L(15); break;
-      case 16: L2L(16); break;
-      default: return hipErrorInvalidValue;
-    }
-#undef L2L
-    return hipGetLastError();
-  }
+  if (v.n_levels == 2 && rhs != y)  // one launch (two-level factor, out of place)
+    return launch_trisolve2(p, trans ? v.urp : v.lrp, trans ? v.uci : v.lci, trans ? v.uval_s : v.lval_s, v.diag, v.n,
+                            rhs, y, st, s);
   const int32_t* rp = trans ? v.urp : v.lrp;
   const int32_t* ci = trans ? v.uci : v.lci;
   const double* va = trans ? v.uval : v.lval;

@@ -398,14 +398,23 @@ __device__ inline T group_sum(T x) {
   return x;
 }
 
-// IDENT: the operator's product with V_k was formed beforehand (the
-// preconditioned operator) and is read row by row from Z instead of gathered.
-template <int P, typename T, bool IDENT = false>
+// OPM selects the operator product the pass starts from:
+//   OP_GATHER  A V_k, gathered through the CSR (rp, ci, va) from V_k;
+//   OP_IDENT   formed beforehand (the preconditioned operator) and read row
+//              by row from Z;
+//   OP_TRI     the forward solve of a two-level IC(0) factor applied to Z on
+//              the fly: (Z_i - sum_e va_e Z_(ci_e)) / diag_i, the CSR being the
+//              factor's strictly lower part with its coefficients divided by
+//              the pivots of the rows they multiply.
+enum { OP_GATHER = 0, OP_IDENT = 1, OP_TRI = 2 };
+template <int P, typename T, int OPM = OP_GATHER>
 __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                               const T* __restrict__ va, int64_t n, T* __restrict__ Vbase,
                                               size_t slot, const T* __restrict__ bench,
                                               double* __restrict__ part, int n_wg, DevState* __restrict__ st,
-                                              const T* __restrict__ Z = nullptr) {
+                                              const T* __restrict__ Z = nullptr,
+                                              const T* __restrict__ diag = nullptr) {
+  constexpr bool IDENT = OPM == OP_IDENT;
   if (st->halt) return;
   using LN = Lanes<P>;
   using Ops = TypeOps<T>;
@@ -467,8 +476,13 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
     // together with the gathered rows (or the CSR entries without the
     // pipeline); its own V_k row is loaded with the gathered rows.
     T v[CPL], w[CPL], vpo[CPL], vp[LN::ROW ? P : 1], g[LN::ROW ? MAXB : 1], gb = T(0);
+    T zr[OPM == OP_TRI ? CPL : 1], dr = T(1);
     auto loads = [&]() {
       if constexpr (!IDENT) pipe.load_ahead(rp, row, r1);
+      if constexpr (OPM == OP_TRI) {  // the row's own entries of Z and its pivot
+        load_own<CPL>((valid && c0 < P) ? Z + row * P + c0 : nullptr, zr);
+        if (valid) dr = diag[row];
+      }
       if constexpr (LN::ROW) {
 #pragma unroll
         for (int r = 0; r < P; ++r) vp[r] = valid ? Vp[row * P + r] : T(0);
@@ -492,9 +506,15 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
       load_own<CPL>(own, v);
       load_own<CPL>((valid && c0 < P) ? Z + row * P + c0 : nullptr, a);
     } else {
-      gather_se<P, LPR, CPL, true, RowPipe<LPR, RPG, T>::PIPE>(ci, va, V, pipe.s_cur, pipe.e_cur, c, a, own, v,
+      // OP_TRI gathers from Z through the factor's pattern, the others from V_k
+      const T* src = OPM == OP_TRI ? Z : V;
+      gather_se<P, LPR, CPL, true, RowPipe<LPR, RPG, T>::PIPE>(ci, va, src, pipe.s_cur, pipe.e_cur, c, a, own, v,
                                                                &pipe.lead, pipe.s_nx, pipe.e_nx, loads);
       pipe.advance();
+      if constexpr (OPM == OP_TRI) {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) a[cc] = (zr[cc] - a[cc]) / dr;
+      }
     }
     if constexpr (LN::ROW) {
       // the lane owns the whole row: everything stays in registers
@@ -676,6 +696,38 @@ __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, con
   }
 }
 
+// A triangular solve of a two-level IC(0) factor in one launch (out of
+// place): y_i = (rhs_i - sum_e va_e rhs_(ci_e)) / diag_i for every row, where
+// (rp, ci, va) is the factor's strictly lower or upper part with each
+// coefficient divided by the pivot of the row it multiplies (every row with
+// entries refers only to rows without any, whose solution is rhs / diag).
+// The gather is the block operator's; the halt flag of st (when given) makes
+// it a no-op.
+template <int P>
+__global__ __launch_bounds__(WG) void k_trisolve2(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                  const double* __restrict__ va, const double* __restrict__ diag,
+                                                  int64_t n, const double* __restrict__ rhs,
+                                                  double* __restrict__ y, int n_wg, const DevState* __restrict__ st) {
+  if (st && st->halt) return;
+  using LN = Lanes<P>;
+  constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / LPR, c = lane % LPR, c0 = c * CPL;
+  int64_t r0, r1;
+  row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
+  for (int64_t base = r0; base < r1; base += RPG) {
+    const int64_t row = base + wave * RPW + grp;
+    const bool valid = row < r1;
+    double a[CPL], own[CPL];
+    load_own<CPL>((valid && c0 < P) ? rhs + row * P + c0 : nullptr, own);
+    const double d = valid ? diag[row] : 1.0;
+    gather_row<P, LPR, CPL>(rp, ci, va, rhs, row, valid, c, a);
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) a[cc] = (own[cc] - a[cc]) / d;
+    if (valid && c0 < P) vstore<CPL>(y + row * P + c0, a);
+  }
+}
+
 // R = B - A X and per-workgroup partial sums of the squared column norms, in
 // FP64 (it is also the outer residual of the mixed-precision solver).
 template <int P>
@@ -835,10 +887,32 @@ template hipError_t launch_spmm<float>(int, const bmr_csr_t&, const float*, cons
 hipError_t launch_pass1_ident(int p, const double* Z, double* Vbase, size_t slot, const double* bench, double* part,
                               int n_wg, int64_t n, DevState* st, hipStream_t s) {
 #define L4(P)                                                                                                   \
-  hipLaunchKernelGGL((k_pass1<P, double, true>), dim3(n_wg), dim3(WG), 0, s, (const int32_t*)nullptr,          \
-                     (const int32_t*)nullptr, (const double*)nullptr, n, Vbase, slot, bench, part, n_wg, st, Z)
+  hipLaunchKernelGGL((k_pass1<P, double, OP_IDENT>), dim3(n_wg), dim3(WG), 0, s, (const int32_t*)nullptr,      \
+                     (const int32_t*)nullptr, (const double*)nullptr, n, Vbase, slot, bench, part, n_wg, st, Z,  \
+                     (const double*)nullptr)
   BMR_DISPATCH_P(p, L4)
 #undef L4
+  return hipGetLastError();
+}
+
+hipError_t launch_trisolve2(int p, const int32_t* rp, const int32_t* ci, const double* va, const double* diag,
+                            int64_t n, const double* rhs, double* y, const DevState* st, hipStream_t s) {
+  const int n_wg = spmm_grid(n, p);
+#define L6(P) \
+  hipLaunchKernelGGL(k_trisolve2<P>, dim3(n_wg), dim3(WG), 0, s, rp, ci, va, diag, n, rhs, y, n_wg, st)
+  BMR_DISPATCH_P(p, L6)
+#undef L6
+  return hipGetLastError();
+}
+
+hipError_t launch_pass1_tri(int p, const int32_t* lrp, const int32_t* lci, const double* lval_s, const double* diag,
+                            const double* Z, double* Vbase, size_t slot, const double* bench, double* part, int n_wg,
+                            int64_t n, DevState* st, hipStream_t s) {
+#define L5(P)                                                                                                    \
+  hipLaunchKernelGGL((k_pass1<P, double, OP_TRI>), dim3(n_wg), dim3(WG), 0, s, lrp, lci, lval_s, n, Vbase, slot, \
+                     bench, part, n_wg, st, Z, diag)
+  BMR_DISPATCH_P(p, L5)
+#undef L5
   return hipGetLastError();
 }
 

@@ -378,12 +378,14 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
           const double* Vk = (const double*)r.Vslot(kq);
           HIP_TRY(launch_ic0_solve(*r.pc, p, true, Vk, r.Y, r.st, r.s));
           HIP_TRY(launch_spmm<double>(p, *r.A, r.A->val, r.Y, r.Z, r.s, r.st));
-          // a two-level factor solves out of place in one launch (Z -> Y),
-          // others level by level in place
-          double* F = r.pc->n_levels == 2 ? r.Y : r.Z;
-          HIP_TRY(launch_ic0_solve(*r.pc, p, false, r.Z, F, r.st, r.s));
-          HIP_TRY(launch_pass1_ident(p, F, (double*)r.V, r.slot, (const double*)r.bench, r.part, r.n_wg, n,
-                                     r.st, r.s));
+          if (r.pc->n_levels == 2) {  // the forward solve inside pass 1
+            HIP_TRY(launch_pass1_tri(p, r.pc->lrp, r.pc->lci, r.pc->lval_s, r.pc->diag, r.Z, (double*)r.V,
+                                     r.slot, (const double*)r.bench, r.part, r.n_wg, n, r.st, r.s));
+          } else {  // level by level in place, then pass 1 on the formed product
+            HIP_TRY(launch_ic0_solve(*r.pc, p, false, r.Z, r.Z, r.st, r.s));
+            HIP_TRY(launch_pass1_ident(p, r.Z, (double*)r.V, r.slot, (const double*)r.bench, r.part, r.n_wg, n,
+                                       r.st, r.s));
+          }
         } else {
           HIP_TRY(launch_pass1<T>(r.p, *r.A, r.val, r.V, r.slot, r.bench, r.part, r.n_wg, r.st, r.s));
         }
