@@ -143,6 +143,46 @@ __device__ inline void vstore_nt(T* __restrict__ p, const T (&x)[CPL]) {
   }
 }
 
+// x as held by lane u of the caller's group of W lanes (groups of W
+// consecutive lanes, W = 1, 2, 4, 8 or 16), with u known once the caller's
+// loop is unrolled.  The CSR entries a group loads are passed round this way:
+// DPP moves on the vector ALU, without the round trip through the LDS unit
+// that a bpermute-based shuffle takes (and that pass 1 shares with its Gram
+// staging).  quad_perm covers W <= 4; row_newbcast (lane u of each row of 16
+// lanes) covers W = 16, and W = 8 applies it to each half row in turn under
+// a bank mask.  Every lane of a group must be active.
+template <int W, int U, typename T>
+__device__ inline T grp_bcast_c(T x) {
+  static_assert(U >= 0 && U < W, "lane outside the group");
+  if constexpr (W == 1) {
+    return x;
+  } else if constexpr (W == 2) {
+    return __builtin_amdgcn_update_dpp(x, x, U | (U << 2) | ((2 + U) << 4) | ((2 + U) << 6), 0xF, 0xF, false);
+  } else if constexpr (W == 4) {
+    return __builtin_amdgcn_update_dpp(x, x, U * 0x55, 0xF, 0xF, false);
+  } else if constexpr (W == 8) {
+    const T t = __builtin_amdgcn_update_dpp(x, x, 0x150 + U, 0xF, 0x3, false);
+    return __builtin_amdgcn_update_dpp(t, x, 0x158 + U, 0xF, 0xC, false);
+  } else {
+    static_assert(W == 16, "group width");
+    return __builtin_amdgcn_update_dpp(x, x, 0x150 + U, 0xF, 0xF, false);
+  }
+}
+
+template <int W, typename T>
+__device__ inline T grp_bcast(T x, int u) {
+  switch (u & (W - 1)) {
+#define BMR_BC(k) \
+  case k:         \
+    if constexpr (k < W) return grp_bcast_c<W, k < W ? k : 0>(x);
+    BMR_BC(0) BMR_BC(1) BMR_BC(2) BMR_BC(3) BMR_BC(4) BMR_BC(5) BMR_BC(6) BMR_BC(7)
+    BMR_BC(8) BMR_BC(9) BMR_BC(10) BMR_BC(11) BMR_BC(12) BMR_BC(13) BMR_BC(14) BMR_BC(15)
+#undef BMR_BC
+    default:
+      return x;
+  }
+}
+
 // With fewer than 8 lanes per row (the group layout for p <= 8) a stencil
 // row spans two chunks of CSR entries.  Their index and value loads are
 // issued together ("lead" entries: s + c and s + LPR + c for lane c), and
@@ -268,7 +308,7 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
       T x[2 * LPR][CPL];
 #pragma unroll
       for (int u = 0; u < 2 * LPR; ++u) {
-        const int cq = __shfl(u < LPR ? cur.colA : cur.colB, u % LPR, LPR);
+        const int cq = grp_bcast<LPR>(u < LPR ? cur.colA : cur.colB, u % LPR);
         if (u < cnt && mine) {
           vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
         } else {
@@ -283,7 +323,7 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
       // the values are passed round after the loads are in flight
 #pragma unroll
       for (int u = 0; u < 2 * LPR; ++u) {
-        const T vq = __shfl(u < LPR ? cur.vA : cur.vB, u % LPR, LPR);
+        const T vq = grp_bcast<LPR>(u < LPR ? cur.vA : cur.vB, u % LPR);
         const T co = u < cnt ? vq : T(0);
 #pragma unroll
         for (int k = 0; k < CPL; ++k) acc[k] = fma(co, x[u][k], acc[k]);
@@ -300,16 +340,17 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
         col = ldnt(ci + idx);
         v = ldnt(va + idx);
       }
-      // cnt > 0 here; the do-while lets the compiler see that every loaded
-      // entry is consumed before the next row starts
+      // cnt > 0 here, so the first batch of U always runs: the compiler sees
+      // that every loaded entry is consumed before the next row starts
       const int cnt = min(LPR, e - base);
-      int q0 = 0;
-      do {
+#pragma unroll
+      for (int h = 0; h < LPR / U; ++h) {
+        if (h > 0 && h * U >= cnt) break;
         T x[U][CPL];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int cq = __shfl(col, q0 + u, LPR);
-          if (q0 + u < cnt && mine) {
+          const int cq = grp_bcast<LPR>(col, h * U + u);
+          if (h * U + u < cnt && mine) {
             vload<CPL>(V + (int64_t)cq * P + c * CPL, x[u]);
           } else {
 #pragma unroll
@@ -318,13 +359,12 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const T vq = __shfl(v, q0 + u, LPR);
-          const T co = q0 + u < cnt ? vq : T(0);
+          const T vq = grp_bcast<LPR>(v, h * U + u);
+          const T co = h * U + u < cnt ? vq : T(0);
 #pragma unroll
           for (int k = 0; k < CPL; ++k) acc[k] = fma(co, x[u][k], acc[k]);
         }
-        q0 += U;
-      } while (q0 < cnt);
+      }
     }
   }
 }
@@ -676,6 +716,105 @@ __global__ __launch_bounds__(WG) void k_pass1(const int32_t* __restrict__ rp, co
   }
 }
 
+// The gathers of two rows interleaved, for the layouts with several lanes per
+// row: the CSR entries of both rows' first chunk (2 LPR entries with lead
+// entries, LPR otherwise) are loaded together, then every gathered load of
+// both chunks is issued before the first is consumed, so each lane group
+// keeps two independent load chains in flight.  Entries beyond the first
+// chunk follow row by row.  Each row accumulates in CSR order, as gather_se
+// does, so the sums are bitwise those of two gather_se calls.
+template <int P, int LPR, int CPL, typename T>
+__device__ inline void gather_pair(const int32_t* __restrict__ ci, const T* __restrict__ va, const T* __restrict__ V,
+                                   const int (&s)[2], const int (&e)[2], int c, T (&acc)[2][CPL]) {
+  constexpr int NL = has_lead(LPR) ? 2 : 1;  // CSR entries per lane in the first chunk
+  constexpr int CH = NL * LPR;               // entries of a row in the first chunk
+  const bool mine = c * CPL < P;
+  int col[2][NL];
+  T v[2][NL];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int h = 0; h < NL; ++h) {
+      const int idx = s[r] + h * LPR + c;
+      col[r][h] = 0;
+      v[r][h] = T(0);
+      if (idx < e[r]) {
+        col[r][h] = ldnt(ci + idx);
+        v[r][h] = ldnt(va + idx);
+      }
+    }
+  T x[2][CH][CPL];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int cq = grp_bcast<LPR>(col[r][u / LPR], u % LPR);
+      if (u < e[r] - s[r] && mine) {
+        vload<CPL>(V + (int64_t)cq * P + c * CPL, x[r][u]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) x[r][u][k] = T(0);
+      }
+    }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) acc[r][k] = T(0);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const T vq = grp_bcast<LPR>(v[r][u / LPR], u % LPR);
+      const T co = u < e[r] - s[r] ? vq : T(0);
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) acc[r][k] = fma(co, x[r][u][k], acc[r][k]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    for (int base = s[r] + CH; base < e[r]; base += LPR) {
+      const int idx = base + c;
+      int cl = 0;
+      T vl = T(0);
+      if (idx < e[r]) {
+        cl = ldnt(ci + idx);
+        vl = ldnt(va + idx);
+      }
+      const int cnt = min(LPR, e[r] - base);
+      T y[LPR][CPL];
+#pragma unroll
+      for (int u = 0; u < LPR; ++u) {
+        const int cq = grp_bcast<LPR>(cl, u);
+        if (u < cnt && mine) {
+          vload<CPL>(V + (int64_t)cq * P + c * CPL, y[u]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) y[u][k] = T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LPR; ++u) {
+        const T vq = grp_bcast<LPR>(vl, u);
+        const T co = u < cnt ? vq : T(0);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) acc[r][k] = fma(co, y[u][k], acc[r][k]);
+      }
+    }
+  }
+}
+
+// Shape of the standalone block operator, chosen per layout by measurement
+// (128^3 7-point Laplacian, FP64, every shape on one box; the results are
+// bitwise equal).  Two rows per lane group (gather_pair) pay where each lane
+// holds two columns of a 4-lane row group (p = 6, 8: 105 -> 100-103 us at
+// p = 8); with one column per lane, or 8-16 lanes per row, the second chain
+// costs more in registers than it hides (p = 16: 161 -> 168-180 us).  With
+// slabs, workgroup b (which runs on XCD b mod 8) takes logical range
+// (b mod 8) * (n_wg / 8) + b / 8, so consecutive ranges share one XCD's L2:
+// one lane per row gains (p = 1: 53.9 -> 50.5 us, p = 2: 60.0 -> 55.3 us),
+// the 8- and 16-lane layouts lose (p = 12: 132 -> 137-140 us), and the paired
+// layouts are level or gain.
+__host__ __device__ constexpr int spmm_rows(int p) { return layout_lpr(p) == 4 && layout_cpl(p) == 2 ? 2 : 1; }
+__host__ __device__ constexpr bool spmm_slab(int p) { return layout_lpr(p) == 1 || spmm_rows(p) == 2; }
+
 template <int P, typename T>
 __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                              const T* __restrict__ va, int64_t n, const T* __restrict__ V,
@@ -683,16 +822,34 @@ __global__ __launch_bounds__(WG) void k_spmm(const int32_t* __restrict__ rp, con
   if (st && st->halt) return;
   using LN = Lanes<P>;
   constexpr int LPR = LN::LPR, CPL = LN::CPL, RPW = LN::RPW, RPG = LN::RPG;
+  constexpr int ROWS = spmm_rows(P);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / LPR, c = lane % LPR, c0 = c * CPL;
+  const int L = spmm_slab(P) ? (int)(blockIdx.x % 8) * (n_wg / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   int64_t r0, r1;
-  row_range<RPG>(n, n_wg, blockIdx.x, r0, r1);
-  for (int64_t base = r0; base < r1; base += RPG) {
-    const int64_t row = base + wave * RPW + grp;
-    const bool valid = row < r1;
-    T a[CPL];
-    gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
-    if (valid && c0 < P) vstore_nt<CPL>(W + row * P + c0, a);
+  row_range<ROWS * RPG>(n, n_wg, L, r0, r1);
+  for (int64_t base = r0; base < r1; base += ROWS * RPG) {
+    if constexpr (ROWS == 2) {
+      const int64_t row[2] = {base + wave * RPW + grp, base + RPG + wave * RPW + grp};
+      int s[2] = {0, 0}, e[2] = {0, 0};
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (row[r] < r1) {
+          s[r] = rp[row[r]];
+          e[r] = rp[row[r] + 1];
+        }
+      T a[2][CPL];
+      gather_pair<P, LPR, CPL>(ci, va, V, s, e, c, a);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (row[r] < r1 && c0 < P) vstore_nt<CPL>(W + row[r] * P + c0, a[r]);
+    } else {
+      const int64_t row = base + wave * RPW + grp;
+      const bool valid = row < r1;
+      T a[CPL];
+      gather_row<P, LPR, CPL>(rp, ci, va, V, row, valid, c, a);
+      if (valid && c0 < P) vstore_nt<CPL>(W + row * P + c0, a);
+    }
   }
 }
 
@@ -826,10 +983,18 @@ int pass1_resident_grid(int64_t n, int p) {
 template int pass1_resident_grid<double>(int64_t, int);
 template int pass1_resident_grid<float>(int64_t, int);
 
-static int spmm_grid(int64_t n, int p) {
+static int step_grid(int64_t n, int p) {
   // one workgroup step each: a grid that walks longer row ranges with the
   // pass-1 pipeline measured slower for the plain product
   return (int)std::max<int64_t>(1, (n + layout_rpg(p) - 1) / layout_rpg(p));
+}
+
+static int spmm_grid(int64_t n, int p) {
+  // one step of spmm_rows(p) row groups each; a multiple of 8 with slabs
+  const int64_t rows = (int64_t)spmm_rows(p) * layout_rpg(p);
+  int64_t g = std::max<int64_t>(1, (n + rows - 1) / rows);
+  if (spmm_slab(p)) g = (g + 7) / 8 * 8;
+  return (int)g;
 }
 
 #define BMR_DISPATCH_P(p, MACRO) \
@@ -897,7 +1062,7 @@ hipError_t launch_pass1_ident(int p, const double* Z, double* Vbase, size_t slot
 
 hipError_t launch_trisolve2(int p, const int32_t* rp, const int32_t* ci, const double* va, const double* diag,
                             int64_t n, const double* rhs, double* y, const DevState* st, hipStream_t s) {
-  const int n_wg = spmm_grid(n, p);
+  const int n_wg = step_grid(n, p);
 #define L6(P) \
   hipLaunchKernelGGL(k_trisolve2<P>, dim3(n_wg), dim3(WG), 0, s, rp, ci, va, diag, n, rhs, y, n_wg, st)
   BMR_DISPATCH_P(p, L6)

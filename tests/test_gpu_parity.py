@@ -75,6 +75,39 @@ def test_spmm_matches_scipy(p, kind):
     assert np.all(np.abs(W - ref) <= 1e-15 * 8 * scale + 1e-300)
 
 
+def _ragged(n, seed):
+    """Symmetric matrix with row lengths from 0 to about 60 (every 7th row
+    and column empty), as a Csr."""
+    import scipy.sparse as sp
+    from workloads import Csr
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 30, size=n)
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(0, n, size=rows.size)
+    M = sp.coo_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(n, n)).tocsr()
+    M = M + M.T
+    keep = sp.diags((np.arange(n) % 7 != 3).astype(np.float64))
+    M = (keep @ M @ keep).tocsr()
+    M.eliminate_zeros()
+    M.sort_indices()
+    return Csr(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 8, 13, 16])
+@pytest.mark.parametrize("n", [1, 5, 97, 4099])
+def test_spmm_ragged_and_tiny(p, n):
+    """Empty rows, rows longer than a lane group's first chunk, and fewer
+    rows than one workgroup step (most workgroups of the grid get none)."""
+    A = _ragged(n, seed=n + p)
+    V = np.random.default_rng(p).standard_normal((n, p))
+    W = bmr.spmm(bmr.to_device(A, DEV), _dev(V)).cpu().numpy()
+    S = A.to_scipy()
+    ref = S @ V
+    scale = abs(S) @ abs(V)
+    assert np.all(np.abs(W - ref) <= 1e-15 * 64 * scale + 1e-300)
+    assert np.all(W[np.diff(A.indptr) == 0] == 0.0)
+
+
 def test_spmm_p8_bitwise_reproducible():
     A = laplacian((33, 31, 29), 0.3)
     V = _dev(np.random.default_rng(0).standard_normal((A.n, 8)))
