@@ -72,6 +72,26 @@ def measured_traffic(workload, kernel):
     return rec.get("bytes_per_launch")
 
 
+def targets(spmm, roofline, fp64_s, mixed, relaxed):
+    """The performance targets, each with the measured figures and whether
+    this run met it."""
+    out = {}
+    fr = {k: spmm[k]["frac"] for k in ("p1", "p8", "p16") if k in spmm}
+    out["spmm_hbm_frac_ge_0.60"] = {**fr, "met": bool(fr) and min(fr.values()) >= 0.60}
+    out["pass1_hbm_frac_ge_0.60"] = {"frac": roofline["frac"], "met": roofline["frac"] >= 0.60}
+    faster = {"fp64_s": round(fp64_s, 4)}
+    if mixed:
+        faster["mixed_refinement_s"] = mixed["value"]
+    if relaxed:
+        faster["relaxed_s"] = relaxed["value"]
+        if "deep" in relaxed:
+            d = relaxed["deep"]
+            faster[f"at_{d['tol']:g}"] = {k: d[k]["value"] for k in ("fp64", "relaxed", "mixed") if k in d}
+    met = [k for k in ("mixed_refinement_s", "relaxed_s") if k in faster and faster[k] < fp64_s]
+    out["mixed_precision_faster_than_fp64"] = {**faster, "met_by": met}
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -206,6 +226,9 @@ def main():
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for hardware byte counters)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-relaxed", action="store_true", help="skip the relaxed-precision leg")
+    ap.add_argument("--deep-tol", type=float, default=1e-10,
+                    help="tolerance of the FP64 / relaxed / mixed comparison beside the bench tol (0: skip)")
     ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--precond-orders", default="redblack",
                     help="comma-separated unknown orderings of the IC(0) leg (natural, redblack; '' to skip)")
@@ -334,6 +357,49 @@ def main():
         log(f"[bench] mixed: {mixed}")
         del Xm, wsm
 
+    # relaxed precision: one solve, FP64 until every recurrence residual is
+    # below min(1e-2, 1e3 tol), then FP32 on the same band state; at the bench
+    # tol and at the deeper tol, beside FP64 (and the mixed refinement there)
+    relaxed = None
+    if not args.no_relaxed:
+        wsr = torch.empty(bmr.workspace_bytes(n, p, nnz=A.nnz, precision="relaxed"), dtype=torch.uint8, device=dev)
+        Xr = torch.empty_like(Bd)
+
+        def timed(**kw):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf = bmr.solve(Ad, Bd, max_iter=max_iter, X=Xr, **kw)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, inf
+
+        rt, rinfo = timed(tol=tol, workspace=wsr, precision="relaxed")
+        relaxed = {"value": round(rt, 6), "unit": "s", "tol": tol, "status": rinfo.status_name,
+                   "relax_tol": min(1e-2, 1e3 * tol), "band_iters": rinfo.band_iters,
+                   "switch_iter": rinfo.switch_iter, "res_explicit_max": float(rinfo.res_explicit.max()),
+                   "x_err_vs_fp64": float((torch.linalg.vector_norm(Xr - X, dim=0)
+                                           / torch.linalg.vector_norm(X, dim=0)).max()),
+                   "vs_fp64": round(rt / (ms_per_step / 1e3), 4)}
+        if args.deep_tol > 0:
+            deep = {"tol": args.deep_tol}
+            d64, i64 = timed(tol=args.deep_tol, workspace=ws)
+            deep["fp64"] = {"value": round(d64, 6), "band_iters": i64.band_iters,
+                            "res_explicit_max": float(i64.res_explicit.max())}
+            drl, irl = timed(tol=args.deep_tol, workspace=wsr, precision="relaxed")
+            deep["relaxed"] = {"value": round(drl, 6), "status": irl.status_name, "band_iters": irl.band_iters,
+                               "switch_iter": irl.switch_iter, "relax_tol": min(1e-2, 1e3 * args.deep_tol),
+                               "res_explicit_max": float(irl.res_explicit.max()), "vs_fp64": round(drl / d64, 4)}
+            if not args.no_mixed:
+                wsm = torch.empty(bmr.workspace_bytes(n, p, nnz=A.nnz, precision="mixed"), dtype=torch.uint8,
+                                  device=dev)
+                dmx, imx = timed(tol=args.deep_tol, workspace=wsm, precision="mixed", inner_tol=args.inner_tol)
+                deep["mixed"] = {"value": round(dmx, 6), "status": imx.status_name, "cycles": imx.n_refine,
+                                 "band_iters": imx.band_iters, "res_explicit_max": float(imx.res_explicit.max()),
+                                 "vs_fp64": round(dmx / d64, 4)}
+                del wsm
+            relaxed["deep"] = deep
+        log(f"[bench] relaxed: {relaxed}")
+        del wsr, Xr
+
     precond = None
     orders = [o for o in args.precond_orders.split(",") if o]
     if orders and args.workload.startswith("lap3d-128"):
@@ -385,6 +451,8 @@ def main():
         "spmm": spmm,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "relaxed": relaxed,
+        "targets": targets(spmm, roofline, ms_per_step / 1e3, mixed, relaxed),
         "random_matrix": rand,
         "ic0": precond,
     }

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define BMR_VERSION 10200 /* 1.2.0 */
+#define BMR_VERSION 10300 /* 1.3.0 */
 #define BMR_MAX_P 16      /* largest block size p */
 #define BMR_MAX_BENCH 4   /* largest substitutes bench */
 
@@ -88,7 +88,7 @@ typedef struct bmr_opts {
   int64_t hist_cap;    /* rows of the residual history kept on the device (>= 0).
                           Default 0. */
   uint32_t flags;      /* BMR_FLAG_* bits.  Default 0. */
-  int32_t precision;   /* BMR_PREC_FP64 (default) or BMR_PREC_MIXED. */
+  int32_t precision;   /* BMR_PREC_FP64 (default), BMR_PREC_MIXED or BMR_PREC_RELAXED. */
   double inner_tol;    /* BMR_PREC_MIXED: each refinement cycle runs the FP32 inner solve
                           until its recurrence residual has dropped by this factor
                           (or below what the outer tolerance still needs).
@@ -96,6 +96,9 @@ typedef struct bmr_opts {
   int32_t max_refine;  /* BMR_PREC_MIXED: refinement cycles at most (>= 1).  Default 30. */
   int32_t precond;     /* BMR_PRECOND_NONE (default) or BMR_PRECOND_IC0: sizes the workspace of
                           bmr_workspace_bytes for bmr_solve_ic0 (bmr_solve accepts NONE only). */
+  double relax_tol;    /* BMR_PREC_RELAXED: the iteration continues in binary32 once every
+                          column's recurrence residual is below relax_tol (relative to
+                          ||b_i||).  0 (default) = min(1e-2, 1e3 * tol); else tol < relax_tol < 1. */
 } bmr_opts_t;
 
 /* bmr_opts_t.precision.
@@ -115,6 +118,28 @@ typedef struct bmr_opts {
  * binary64 residual, not on the recurrence. */
 #define BMR_PREC_FP64 0
 #define BMR_PREC_MIXED 1
+/* BMR_PREC_RELAXED: one run of the solver of Algorithm 7.1 (not part of the
+ * paper), in binary64 until every column's recurrence residual is below
+ * relax_tol, then with the block operator, the Gram products, the update
+ * pass, the Lanczos blocks and the bench in binary32 as in BMR_PREC_MIXED's
+ * inner solve (the band kernel stays binary64), without a restart: at the
+ * end of a group of blocks the two Lanczos blocks the iteration needs next
+ * and the bench are rounded to binary32, while the search directions and X
+ * stay binary64 (the flush reads the binary32 blocks into binary64 sums;
+ * the search directions' three-term recurrence would otherwise carry
+ * binary32 rounding at the scale of the whole solution into the residual
+ * gap).  This is a relaxed-accuracy inexact Krylov method: a product's error
+ * may grow as the residual falls (Simoncini and Szyld, SIAM J. Sci. Comput.
+ * 25, 2003; van den Eshof and Sleijpen, SIAM J. Matrix Anal. Appl. 26,
+ * 2004): the error a product may carry grows like tol * sigma_min(A) /
+ * ||r_j||, so binary32 rounding (u = 2^-24 of ||A||) may enter once the
+ * residual is below about tol * sigma_min(A) / (u ||A||).  The default
+ * switch level 1e3 * tol keeps the explicit residual at tol on a 7-point
+ * Laplacian with condition number 4e4; better conditioned systems allow a
+ * larger relax_tol, worse ones need a smaller.  The stopping test is on
+ * the recurrence, as for BMR_PREC_FP64; res_explicit reports the explicit
+ * residual.  Not with BMR_FLAG_RETAIN. */
+#define BMR_PREC_RELAXED 2
 
 /* bmr_opts_t.precond. */
 #define BMR_PRECOND_NONE 0
@@ -170,6 +195,8 @@ typedef struct bmr_stats {
                                      0 where b_i = 0 */
   int32_t n_retained;      /* BMR_FLAG_RETAIN: removed candidates kept */
   int32_t _pad;
+  int64_t switch_iter;     /* BMR_PREC_RELAXED: band iterations run in binary64 before the
+                              switch to binary32 (0: the solve ended before it) */
 } bmr_stats_t;
 
 /* Library version, BMR_VERSION of the build. */

@@ -48,7 +48,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("gamma", ctypes.c_double),
                 ("n_bench", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("hist_cap", ctypes.c_int64), ("flags", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("relax_tol", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -57,14 +58,16 @@ class _Stats(ctypes.Structure):
                 ("res_rec", ctypes.c_double * MAX_P), ("time_ms", ctypes.c_double),
                 ("t_kernel_ms", ctypes.c_double * 4), ("n_profiled", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32), ("res_true", ctypes.c_double * MAX_P),
-                ("res_explicit", ctypes.c_double * MAX_P), ("n_retained", ctypes.c_int32), ("_pad", ctypes.c_int32)]
+                ("res_explicit", ctypes.c_double * MAX_P), ("n_retained", ctypes.c_int32), ("_pad", ctypes.c_int32),
+                ("switch_iter", ctypes.c_int64)]
 
 FLAG_PROFILE = 1
 FLAG_RETAIN = 2
 FLAG_ACCUMULATE = 4
 PREC_FP64 = 0
 PREC_MIXED = 1
-_PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
+PREC_RELAXED = 2
+_PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED, "relaxed": PREC_RELAXED}
 KERNEL_NAMES = ("pass1_spmm_gram", "reduce", "band", "pass2_update")
 
 
@@ -172,7 +175,7 @@ def _check_block(t, n, name, dtype=None):
 
 
 def _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, flags=0, precision="fp64", inner_tol=None,
-          max_refine=None) -> _Opts:
+          max_refine=None, relax_tol=None) -> _Opts:
     o = _Opts()
     load().bmr_default_opts(ctypes.byref(o))
     o.tol, o.max_iter, o.gamma, o.n_bench = float(tol), int(max_iter), float(gamma), int(n_bench)
@@ -185,12 +188,14 @@ def _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every, flags=0, pr
         o.inner_tol = float(inner_tol)
     if max_refine is not None:
         o.max_refine = int(max_refine)
+    if relax_tol is not None:
+        o.relax_tol = float(relax_tol)
     return o
 
 
 def workspace_bytes(n: int, p: int, n_bench: int = 2, hist_cap: int = 0, nnz: int = 0,
                     precision: str = "fp64", precond: str = "none", retain: bool = False) -> int:
-    """Device workspace bytes of a solve (nnz matters for precision="mixed";
+    """Device workspace bytes of a solve (nnz matters for precision="mixed" and "relaxed";
     precond="ic0" for a preconditioned solve; retain for kept candidates)."""
     o = _opts(1e-8, 1, 1e-10, n_bench, 0, hist_cap, 0, flags=FLAG_RETAIN if retain else 0, precision=precision)
     o.precond = _PRECONDS[precond]
@@ -217,6 +222,7 @@ class SolveInfo:
     res_true: Optional[np.ndarray] = None  # final explicit relative residual (precision="mixed")
     res_explicit: Optional[np.ndarray] = None  # explicit ||b_i - A x_i|| / ||b_i|| of the returned X
     n_retained: int = 0                # removed candidates kept (retain=True)
+    switch_iter: int = 0               # precision="relaxed": band iterations run in FP64 before the switch
 
     @property
     def status_name(self) -> str:
@@ -268,13 +274,15 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
           seed: int = 0, hist_cap: int = 0, poll_every: int = 0, X=None, workspace=None, check: bool = True,
           profile: bool = False, precision: str = "fp64", inner_tol: Optional[float] = None,
           max_refine: Optional[int] = None, ic0: Optional[Ic0] = None, retain: bool = False,
-          accumulate: bool = False):
+          accumulate: bool = False, relax_tol: Optional[float] = None):
     """Solve A X = B (A symmetric) by band-Lanczos block MINRES on the GPU.
 
     B: contiguous float64 (n, p) CUDA tensor.  Returns (X, SolveInfo).
     precision="mixed" runs the FP32 inner solver inside FP64 iterative
     refinement (inner_tol, max_refine: see bmr_opts_t); its hist rows are the
-    explicit relative residuals after each refinement cycle.  ``retain``
+    explicit relative residuals after each refinement cycle.  precision=
+    "relaxed" runs one solve in FP64 until every recurrence residual is below
+    relax_tol (default min(1e-2, 1e3 tol)), then in FP32 (BMR_PREC_RELAXED).  ``retain``
     keeps removed candidates (BMR_FLAG_RETAIN), ``accumulate`` applies the
     previous blocks' rotations as accumulated matrices (BMR_FLAG_ACCUMULATE).
     With ``ic0``
@@ -293,7 +301,7 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
     o = _opts(tol, max_iter, gamma, n_bench, seed, hist_cap, poll_every,
               (FLAG_PROFILE if profile else 0) | (FLAG_RETAIN if retain else 0)
               | (FLAG_ACCUMULATE if accumulate else 0),
-              precision, inner_tol, max_refine)
+              precision, inner_tol, max_refine, relax_tol)
     if ic0 is not None:
         o.precond = PRECOND_IC0
     need = ctypes.c_size_t()
@@ -322,6 +330,7 @@ def solve(A: DeviceCsr, B, tol: float = 1e-8, max_iter: int = 10000, gamma: floa
     info.precision = precision
     info.res_explicit = np.array(stats.res_explicit[:p])
     info.n_retained = int(stats.n_retained)
+    info.switch_iter = int(stats.switch_iter)
     if precision == "mixed":
         info.n_refine = int(stats.n_refine)
         info.res_true = np.array(stats.res_true[:p])

@@ -152,9 +152,12 @@ constexpr double RETAIN_FLOOR = 1.0 / 67108864.0;
 // and the bench hold the storage type of the solve (8 bytes for FP64, 4 for
 // the FP32 inner solve of BMR_PREC_MIXED); the mixed-precision solver also
 // keeps the FP32 matrix values, the FP32 correction D and the FP64 residual R.
+// BMR_PREC_RELAXED holds the FP64 blocks and, beside them, the FP32 ring,
+// bench and matrix values it switches to.
 struct Layout {
   size_t off_state, off_red, off_part, off_hist, off_V, off_M, off_bench;
-  size_t off_val32, off_D, off_R;  // BMR_PREC_MIXED only
+  size_t off_val32, off_D, off_R;  // BMR_PREC_MIXED; BMR_PREC_RELAXED uses off_val32
+  size_t off_V32, off_bench32;  // BMR_PREC_RELAXED only: the FP32 ring and bench after the switch
   size_t off_Y, off_Z;             // BMR_PRECOND_IC0 only: two n x p blocks for the operator
   size_t off_ret;                  // BMR_FLAG_RETAIN only: retained candidates, n x nb
   size_t total;
@@ -234,6 +237,10 @@ hipError_t launch_pass2(int p, T* Vbase, size_t slot_elems, T* bench, int64_t n,
 template <typename T>
 hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot_elems, T* X, int64_t n, int64_t k,
                         const DevState* st, hipStream_t s);
+// The flush with the ring's Lanczos blocks in FP32 and the search directions
+// and X in FP64 (BMR_PREC_RELAXED after its switch).
+hipError_t launch_flush_vf(int p, const float* Vbase, double* Mbase, size_t slot_elems, double* X, int64_t n,
+                           int64_t k, const DevState* st, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s);
 template <typename T>

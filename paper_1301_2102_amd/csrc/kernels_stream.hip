@@ -226,9 +226,12 @@ __device__ __attribute__((always_inline)) inline void rows_in_batch(const T* con
   }
 }
 
-template <int P, typename T>
+// TV: storage type of the Lanczos blocks in the ring; T: that of the search
+// directions and X (FP32 blocks with FP64 search directions and X after the
+// switch of BMR_PREC_RELAXED).
+template <int P, typename T, typename TV = T>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(P)))) void k_flush(
-    const T* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot, T* __restrict__ X, int64_t n, int64_t kexp,
+    const TV* __restrict__ Vbase, T* __restrict__ Mbase, size_t slot, T* __restrict__ X, int64_t n, int64_t kexp,
     const DevState* __restrict__ st) {
   if (st->flush_block != kexp || st->flush_len == 0) return;
   constexpr int S = group_len(P), R = ring_len(P);
@@ -237,7 +240,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
   const int64_t g = kexp - m;
   T* __restrict__ Ma = Mbase;         // M_{g-1}, then M_{g+m-1}
   T* __restrict__ Mb = Mbase + slot;  // M_g, then M_{g+m}
-  if constexpr (sizeof(T) == 8 && P <= 8) {
+  constexpr bool SAME = sizeof(TV) == sizeof(T);
+  if constexpr (sizeof(T) == 8 && SAME && P <= 8) {
     // FP64, p <= 8: the rows move through the LDS tile as in pass 2, and the
     // wave-uniform coefficients are read from the state record (scalar
     // loads) rather than staged in LDS, which leaves the tile as the only
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
   // lane; there the tile's LDS would cost a workgroup per CU (3 -> 2) and the
   // staged form was slower (pass 2 + flush 0.114 -> 0.125 ms at p = 8).
   // FP32 keeps one row per lane, as in its pass 2.
-  if constexpr (P > 8 && sizeof(T) == 8) {
+  if constexpr (P > 8 && sizeof(T) == 8 && SAME) {
     __shared__ T stile[WG / 64][64 * (P + 1)];
     const int lane = threadIdx.x & 63;
     T* tile = stile[threadIdx.x >> 6];
@@ -357,9 +361,12 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(flush_waves(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int i = i0 + u;
-          if (i < m + 2) {
-            const T* __restrict__ src =
-                i < m ? Vbase + (size_t)((g + 1 + i) % R) * slot : (i == m ? Mb : Ma);
+          if (i < m) {
+            const TV* __restrict__ src = Vbase + (size_t)((g + 1 + i) % R) * slot;
+#pragma unroll
+            for (int c = 0; c < P; ++c) x[u][c] = (T)src[row * P + c];
+          } else if (i < m + 2) {
+            const T* __restrict__ src = i == m ? Mb : Ma;
 #pragma unroll
             for (int c = 0; c < P; ++c) x[u][c] = src[row * P + c];
           }
@@ -550,8 +557,20 @@ hipError_t launch_pass2(int p, T* Vbase, size_t slot, T* bench, int64_t n, DevSt
 template <typename T>
 hipError_t launch_flush(int p, const T* Vbase, T* Mbase, size_t slot, T* X, int64_t n, int64_t k, const DevState* st,
                         hipStream_t s) {
+  if (!Vbase || !Mbase || !X || !st) return hipErrorInvalidValue;
   const int g = stream_grid(n);
 #define L5(P) hipLaunchKernelGGL((k_flush<P, T>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, n, k, st)
+  BMR_DISPATCH_P(p, L5)
+#undef L5
+  return hipGetLastError();
+}
+
+hipError_t launch_flush_vf(int p, const float* Vbase, double* Mbase, size_t slot, double* X, int64_t n, int64_t k,
+                           const DevState* st, hipStream_t s) {
+  if (!Vbase || !Mbase || !X || !st) return hipErrorInvalidValue;
+  const int g = stream_grid(n);
+#define L5(P) \
+  hipLaunchKernelGGL((k_flush<P, double, float>), dim3(g), dim3(WG), 0, s, Vbase, Mbase, slot, X, n, k, st)
   BMR_DISPATCH_P(p, L5)
 #undef L5
   return hipGetLastError();
@@ -567,6 +586,7 @@ static unsigned flat_grid(size_t count) {
 template <typename T>
 hipError_t launch_fill(T* x, size_t count, T v, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (!x) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fill<T>, dim3(flat_grid(count)), dim3(WG), 0, s, x, count, v);
   return hipGetLastError();
 }
@@ -587,18 +607,21 @@ hipError_t launch_coldots(const T* Y, int ldy, int yc, const T* X, int ldx, int 
 
 hipError_t launch_to_f32(const double* src, float* dst, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (!src || !dst) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_to_f32, dim3(flat_grid(count)), dim3(WG), 0, s, src, dst, count);
   return hipGetLastError();
 }
 
 hipError_t launch_add_f32(double* x, const float* d, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (!x || !d) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_add_f32, dim3(flat_grid(count)), dim3(WG), 0, s, x, d, count);
   return hipGetLastError();
 }
 
 hipError_t launch_copy(const double* src, double* dst, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (!src || !dst) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_copy, dim3(flat_grid(count)), dim3(WG), 0, s, src, dst, count);
   return hipGetLastError();
 }

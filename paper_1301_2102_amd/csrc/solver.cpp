@@ -45,6 +45,8 @@ constexpr double GAMMA_F32 = 1e-5;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 size_t slot_elems(int64_t n, int p) { return ((size_t)n * p + 31) / 32 * 32; }
 
+static_assert(sizeof(bmr_opts_t) == 80 && sizeof(bmr_stats_t) == 488, "the Python binding mirrors these");
+
 struct Ctl {  // leading fields of DevState polled by the host
   int halt, status, reason, taken;
   int64_t k, k2, j;
@@ -77,6 +79,9 @@ struct Run {
   const Ic0View* pc = nullptr;
   double *Y = nullptr, *Z = nullptr;
   T* ret = nullptr;  // retained removed candidates (n x nb), or NULL
+  // FP32 run after the switch of BMR_PREC_RELAXED: the search directions and
+  // X stay FP64 (the flush reads the FP32 ring into FP64 sums)
+  double *M64 = nullptr, *X64 = nullptr;
 
   T* Vslot(int64_t k) { return V + (size_t)(k % ring_len(p)) * slot; }
 
@@ -113,6 +118,7 @@ struct Run {
 Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int precision, int precond,
                   bool retain) {
   const bool mixed = precision == BMR_PREC_MIXED;
+  const bool relaxed = precision == BMR_PREC_RELAXED;
   const size_t esz = mixed ? sizeof(float) : sizeof(double);
   Layout L{};
   L.n_wg = pass1_grid(n, p);
@@ -142,6 +148,14 @@ Layout layout_for(int64_t n, int64_t nnz, int p, int nb, int64_t hist_cap, int p
     off = align256(off + sizeof(float) * (size_t)n * p);
     L.off_R = off;
     off = align256(off + sizeof(double) * (size_t)n * p);
+  }
+  if (relaxed) {
+    L.off_V32 = off;
+    off = align256(off + sizeof(float) * ring_len(p) * se);
+    L.off_bench32 = off;
+    off = align256(off + sizeof(float) * (size_t)n * nb);
+    L.off_val32 = off;
+    off = align256(off + sizeof(float) * (size_t)nnz);
   }
   if (retain) {
     L.off_ret = off;
@@ -180,8 +194,10 @@ namespace {
 bool opts_valid(const bmr_opts_t& o) {
   return o.tol > 0.0 && isfinite(o.tol) && o.max_iter >= 1 && o.gamma >= 0.0 && isfinite(o.gamma) &&
          o.n_bench >= 0 && o.n_bench <= BMR_MAX_BENCH && o.hist_cap >= 0 && o.poll_every >= 0 &&
-         (o.precision == BMR_PREC_FP64 || o.precision == BMR_PREC_MIXED) &&
-         (o.precision == BMR_PREC_FP64 || (o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_refine >= 1)) &&
+         (o.precision == BMR_PREC_FP64 || o.precision == BMR_PREC_MIXED || o.precision == BMR_PREC_RELAXED) &&
+         (o.precision != BMR_PREC_MIXED || (o.inner_tol > 0.0 && o.inner_tol < 1.0 && o.max_refine >= 1)) &&
+         (o.precision != BMR_PREC_RELAXED ||
+          ((o.relax_tol == 0.0 || (o.relax_tol > o.tol && o.relax_tol < 1.0)) && !(o.flags & BMR_FLAG_RETAIN))) &&
          (o.precond == BMR_PRECOND_NONE || (o.precond == BMR_PRECOND_IC0 && o.precision == BMR_PREC_FP64));
 }
 
@@ -192,13 +208,18 @@ bool csr_valid(const bmr_csr_t* A) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-// The two pinned status records the host polls, allocated for one run of
-// the block-iteration driver and freed at its end.
+// The two pinned status records the host polls (the head of the state and,
+// for the switch of BMR_PREC_RELAXED, the last residuals), allocated for one
+// run of the block-iteration driver and freed at its end.
+struct PinRec {
+  Ctl ctl;
+  double rho[MAXP];
+};
 struct PinnedCtl {
-  Ctl* buf = nullptr;
+  PinRec* buf = nullptr;
   PinnedCtl() {
     void* p = nullptr;
-    if (hipHostMalloc(&p, 2 * sizeof(Ctl), hipHostMallocDefault) == hipSuccess) buf = (Ctl*)p;
+    if (hipHostMalloc(&p, 2 * sizeof(PinRec), hipHostMallocDefault) == hipSuccess) buf = (PinRec*)p;
   }
   ~PinnedCtl() {
     if (buf) (void)hipHostFree(buf);
@@ -216,7 +237,15 @@ struct CoreParams {
   bool prof;
   const double* beta_stop;  // per-column scale of the stopping test, or NULL for ||b_i||
   bool accumulate = false;  // apply the previous blocks' rotations as accumulated matrices
+  // BMR_PREC_RELAXED.  switch_theta > 0: once every column's residual is
+  // below it, run to the end of the current group of blocks and return
+  // SWITCHED with the device state intact.  resume_k > 0: no set-up; the
+  // device state (at the end of a group) goes on from block resume_k.
+  double switch_theta = 0.0;
+  int64_t resume_k = 0;
 };
+// Internal return of the driver: stopped for the switch to binary32.
+constexpr int SWITCHED = 1000;
 struct CoreOut {
   int64_t j = 0, k = 0;
   int n_replaced = 0, n_explicit = 0, n_kept = 0;
@@ -232,17 +261,31 @@ template <typename T>
 int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& out, double* res_hist) {
   const int p = r.p, nb = r.nb;
   const int64_t n = r.n;
-  // ---- set-up -------------------------------------------------------------
-  HIP_TRY(launch_fill<T>(r.V, ring_len(p) * r.slot, T(0), r.s));
-  HIP_TRY(launch_fill<T>(r.M, 2 * r.slot, T(0), r.s));
-  HIP_TRY(launch_fill<T>(X, (size_t)n * p, T(0), r.s));
-  HIP_TRY(launch_bench_init<T>(r.bench, n, nb, o.seed, r.s));
-
   DevState* hs = new DevState();
   struct Guard {
     DevState* p;
     ~Guard() { delete p; }
   } guard{hs};
+  auto finish = [&](int64_t j, int64_t kblocks, const double* rho) {
+    out.j = j;
+    out.k = kblocks;
+    out.n_replaced = hs->n_replaced;
+    out.n_explicit = hs->n_explicit;
+    out.n_kept = hs->n_kept;
+    for (int i = 0; i < MAXP; ++i) out.rho[i] = (i < p && rho) ? rho[i] : 0.0;
+  };
+  if (o.resume_k > 0) {
+    // the device state of a run stopped at SWITCHED: the ring, the search
+    // directions, X and the bench go on as they are (nothing is cleared)
+    HIP_TRY(hipMemcpyAsync(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost, r.s));
+    HIP_TRY(hipStreamSynchronize(r.s));
+    for (int i = 0; i < p; ++i) out.bnorm[i] = hs->beta[i];
+  } else {
+  // ---- set-up -------------------------------------------------------------
+  HIP_TRY(launch_fill<T>(r.V, ring_len(p) * r.slot, T(0), r.s));
+  HIP_TRY(launch_fill<T>(r.M, 2 * r.slot, T(0), r.s));
+  HIP_TRY(launch_fill<T>(X, (size_t)n * p, T(0), r.s));
+  HIP_TRY(launch_bench_init<T>(r.bench, n, nb, o.seed, r.s));
   memset(hs, 0, sizeof(DevState));
   hs->status = STATUS_RUNNING;
   hs->p = p;
@@ -271,14 +314,6 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     TRY(r.coldots(r.bench, nb, b, (const T*)nullptr, 0, 0, c));
     hs->bench_norm0[b] = sqrt(c[0]);
   }
-  auto finish = [&](int64_t j, int64_t kblocks, const double* rho) {
-    out.j = j;
-    out.k = kblocks;
-    out.n_replaced = hs->n_replaced;
-    out.n_explicit = hs->n_explicit;
-    out.n_kept = hs->n_kept;
-    for (int i = 0; i < MAXP; ++i) out.rho[i] = (i < p && rho) ? rho[i] : 0.0;
-  };
   // initial QR of F_0 = B into V_1 (slot 1): copy (rounded to T), then
   // column-wise CGS2 on the device against the reference norms ||b_i||
   for (int i = 0; i < p; ++i) hs->qr_ref[i] = bnorm[i];
@@ -316,10 +351,11 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     return BMR_CONVERGED;
   }
   HIP_TRY(hipMemcpyAsync(r.st, hs, sizeof(DevState), hipMemcpyHostToDevice, r.s));
+  }  // set-up
 
   // ---- block iterations -------------------------------------------------
   PinnedCtl pinned;
-  Ctl* pin = pinned.buf;
+  PinRec* pin = pinned.buf;
   if (!pin) return BMR_HIP_ERROR;
   hipEvent_t ev[2];
   HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -365,8 +401,14 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
   // iterations end a group of search directions and enqueues the flush
   // after them; the flush checks the block number the band kernel recorded.
   const int grp = group_len(p);
-  int64_t kq = 1;
+  int64_t kq = o.resume_k > 0 ? o.resume_k : 1;
   auto flush = [&](int64_t kb) -> int {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (r.M64) {
+        HIP_TRY(launch_flush_vf(r.p, r.V, r.M64, r.slot, r.X64, r.n, kb, r.st, r.s));
+        return 0;
+      }
+    }
     HIP_TRY(launch_flush<T>(r.p, r.V, r.M, r.slot, X, r.n, kb, r.st, r.s));
     return 0;
   };
@@ -401,7 +443,10 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
       if (kq % grp == 0) TRY(flush(kq));
       if (prof) HIP_TRY(hipEventRecord(pev[slot][4], r.s));
     }
-    HIP_TRY(hipMemcpyAsync(&pin[slot], r.st, sizeof(Ctl), hipMemcpyDeviceToHost, r.s));
+    HIP_TRY(hipMemcpyAsync(&pin[slot].ctl, r.st, sizeof(Ctl), hipMemcpyDeviceToHost, r.s));
+    if (o.switch_theta > 0)
+      HIP_TRY(hipMemcpyAsync(pin[slot].rho, (const char*)r.st + offsetof(DevState, rho), sizeof(double) * MAXP,
+                             hipMemcpyDeviceToHost, r.s));
     HIP_TRY(hipEventRecord(ev[slot], r.s));
     return 0;
   };
@@ -410,15 +455,42 @@ int solve_core(Run<T>& r, const double* B, T* X, const CoreParams& o, CoreOut& o
     TRY(enq(0));
     int cur = 0;
     Ctl ctl{};
+    bool drain = false;
     for (;;) {
       if (!prof) TRY(enq(cur ^ 1));
       HIP_TRY(hipEventSynchronize(ev[cur]));
-      ctl = pin[cur];
+      ctl = pin[cur].ctl;
       // a halted iteration's kernels returned at once: time only live ones
       if (prof && (!ctl.halt || ctl.reason == REASON_FINISHED)) TRY(collect(cur));
       if (ctl.halt) break;
+      if (o.switch_theta > 0) {
+        double w = 0.0;
+        for (int i = 0; i < p; ++i) w = std::max(w, pin[cur].rho[i]);
+        if (w < o.switch_theta) {
+          drain = true;
+          break;
+        }
+      }
       if (prof) TRY(enq(cur ^ 1));
       cur ^= 1;
+    }
+    if (drain) {
+      // enqueue up to the end of the group the last enqueued block is in,
+      // let the device finish, and hand over unless it halted meanwhile
+      const int64_t target = (kq - 1 + grp - 1) / grp * grp;
+      if (kq <= target) {
+        const int keep = batch;
+        batch = (int)(target - kq + 1);
+        TRY(enq(cur));  // slot cur: its record has been read
+        batch = keep;
+      }
+      HIP_TRY(hipStreamSynchronize(r.s));
+      HIP_TRY(hipMemcpy(hs, r.st, sizeof(DevState), hipMemcpyDeviceToHost));
+      if (!hs->halt) {
+        finish(hs->j, hs->k, hs->rho);
+        return SWITCHED;
+      }
+      memcpy(&ctl, hs, sizeof(Ctl));
     }
     if (ctl.reason != REASON_EXPLICIT_QR) {
       HIP_TRY(hipStreamSynchronize(r.s));
@@ -608,6 +680,82 @@ int solve_mixed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr
   return status;
 }
 
+// BMR_PREC_RELAXED: the FP64 driver until every column's recurrence
+// residual is below relax_tol and the current group of blocks has ended,
+// then the FP32 driver on the same device state: V_k and V_{k-1} of the next
+// block and the bench are rounded to FP32, tau_fb and gamma take the FP32
+// values, and the flush reads the FP32 ring into the FP64 search directions
+// and X.  Keeping those two FP64 matters: the search directions follow a
+// three-term recurrence, M_k = (V_k - M_{k-1} D_k - M_{k-2} E_k) C_k, whose
+// rounding errors MINRES's residual gap grows with, and they are of the size
+// of the whole solution, not of the error left at the switch.
+int solve_relaxed(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_opts_t& o, char* ws,
+                  const Layout& L, hipStream_t s, bmr_stats_t* stats, double* res_hist) {
+  const int64_t n = A->n;
+  Run<double> r{};
+  bind(r, A, A->val, p, o.n_bench, s, ws, L);
+  const bool prof = (o.flags & BMR_FLAG_PROFILE) != 0, acc = (o.flags & BMR_FLAG_ACCUMULATE) != 0;
+  CoreParams cp{o.tol, o.gamma, TAU_FB, o.max_iter, o.hist_cap, o.seed, o.poll_every, prof, nullptr, acc};
+  cp.switch_theta = o.relax_tol > 0 ? o.relax_tol : std::min(1e-2, 1e3 * o.tol);
+  CoreOut out;
+  int status = solve_core<double>(r, B, X, cp, out, res_hist);
+  if (status < 0) return status;
+  int64_t switch_j = 0;
+  CoreOut tot = out;
+  if (status == SWITCHED) {
+    switch_j = out.j;
+    const int64_t k = out.k;  // the next block; blocks up to k - 1 are flushed into X
+    float* val32 = (float*)(ws + L.off_val32);
+    Run<float> q{};
+    q.A = A;
+    q.val = val32;
+    q.p = p;
+    q.nb = o.n_bench;
+    q.n = n;
+    q.s = s;
+    q.n_wg = pass1_resident_grid<float>(n, p);  // <= L.n_wg, which sizes the partial sums
+    q.st = r.st;
+    q.red = r.red;
+    q.part = r.part;
+    q.hist = r.hist;
+    q.V = (float*)(ws + L.off_V32);
+    q.M = nullptr;
+    q.M64 = r.M;
+    q.X64 = X;
+    q.bench = (float*)(ws + L.off_bench32);
+    q.slot = r.slot;
+    HIP_TRY(launch_to_f32(A->val, val32, (size_t)A->nnz, s));
+    HIP_TRY(launch_to_f32(r.Vslot(k), q.Vslot(k), (size_t)n * p, s));
+    HIP_TRY(launch_to_f32(r.Vslot(k - 1), q.Vslot(k - 1), (size_t)n * p, s));
+    if (o.n_bench > 0) HIP_TRY(launch_to_f32(r.bench, q.bench, (size_t)n * o.n_bench, s));
+    const double gt[2] = {std::max(o.gamma, GAMMA_F32), TAU_FB_F32};  // DevState: gamma, tau_fb
+    static_assert(offsetof(DevState, tau_fb) == offsetof(DevState, gamma) + sizeof(double), "gamma, tau_fb");
+    HIP_TRY(hipMemcpyAsync((char*)r.st + offsetof(DevState, gamma), gt, sizeof(gt), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    CoreParams cq{o.tol, gt[0], TAU_FB_F32, o.max_iter, o.hist_cap, o.seed, o.poll_every, prof, nullptr, acc};
+    cq.resume_k = k;
+    CoreOut o32;
+    status = solve_core<float>(q, nullptr, nullptr, cq, o32, res_hist);
+    if (status < 0) return status;
+    tot.j = o32.j;  // the device counters run on across the switch
+    tot.k = o32.k;
+    tot.n_replaced = o32.n_replaced;
+    tot.n_explicit = o32.n_explicit;
+    tot.n_kept = o32.n_kept;
+    for (int i = 0; i < MAXP; ++i) tot.rho[i] = o32.rho[i];
+    for (int c = 0; c < 4; ++c) tot.tk[c] += o32.tk[c];
+    tot.n_prof += o32.n_prof;
+  }
+  double rn[MAXP];
+  TRY(residual_norms(A, B, X, p, nullptr, r.part, L.n_wg, r.red, s, rn));
+  fill_stats(stats, status, p, tot);
+  if (stats) {
+    for (int i = 0; i < p; ++i) stats->res_explicit[i] = out.bnorm[i] > 0 ? rn[i] / out.bnorm[i] : 0.0;
+    stats->switch_iter = switch_j;
+  }
+  return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -644,6 +792,7 @@ void bmr_default_opts(bmr_opts_t* o) {
   o->precision = BMR_PREC_FP64;
   o->inner_tol = 1e-6;
   o->max_refine = 30;
+  o->relax_tol = 0.0;
 }
 
 int bmr_workspace_bytes(int64_t n, int64_t nnz, int p, const bmr_opts_t* opts, size_t* bytes) {
@@ -673,6 +822,8 @@ int bmr_solve(const bmr_csr_t* A, const double* B, double* X, int p, const bmr_o
   (void)hipEventRecord(t0, stream);
   const int status = o.precision == BMR_PREC_MIXED
                          ? solve_mixed(A, B, X, p, o, (char*)workspace, L, stream, stats, res_hist)
+                     : o.precision == BMR_PREC_RELAXED
+                         ? solve_relaxed(A, B, X, p, o, (char*)workspace, L, stream, stats, res_hist)
                          : solve_fp64(A, B, X, p, o, (char*)workspace, L, stream, stats, res_hist);
   (void)hipEventRecord(t1, stream);
   (void)hipEventSynchronize(t1);

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.bmr_version() == 10200
+    assert lib.bmr_version() == 10300
     for code, word in [(0, "converged"), (1, "maximum"), (2, "bench"), (3, "stagnated"), (-1, "invalid"),
                        (-2, "workspace"), (-3, "HIP"), (-4, "non-finite"), (-5, "singular")]:
         assert word in bmr.status_string(code)
@@ -43,7 +43,8 @@ def test_default_opts(lib):
     lib.bmr_default_opts(ctypes.byref(o))
     assert (o.tol, o.max_iter, o.gamma, o.n_bench, o.seed, o.hist_cap, o.flags) == (1e-8, 10000, 1e-10, 2, 0, 0, 0)
     assert (o.precision, o.inner_tol, o.max_refine) == (bmr.PREC_FP64, 1e-6, 30)
-    assert ctypes.sizeof(bmr._Opts) == 72 and ctypes.sizeof(bmr._Stats) == 480  # sizeof in C
+    assert ctypes.sizeof(bmr._Opts) == 80 and ctypes.sizeof(bmr._Stats) == 488  # static_assert in C
+    assert o.relax_tol == 0.0
 
 
 def test_workspace_bytes(lib):
@@ -68,11 +69,25 @@ def test_workspace_bytes(lib):
     for bad in [(0, 0, 8), (10, 0, 0), (10, 0, 17), (10, -1, 4)]:
         assert lib.bmr_workspace_bytes(bad[0], bad[1], bad[2], None, ctypes.byref(out)) == bmr.INVALID_ARG
     o = bmr._Opts()
-    for field, value in [("precision", 2), ("inner_tol", 0.0), ("inner_tol", 1.0), ("max_refine", 0)]:
+    for field, value in [("precision", 3), ("inner_tol", 0.0), ("inner_tol", 1.0), ("max_refine", 0)]:
         lib.bmr_default_opts(ctypes.byref(o))
         o.precision = bmr.PREC_MIXED
         setattr(o, field, value)
         assert lib.bmr_workspace_bytes(10, 28, 4, ctypes.byref(o), ctypes.byref(out)) == bmr.INVALID_ARG
+    # relaxed precision: the FP64 blocks, and beside them the FP32 ring, bench
+    # and matrix values
+    wr = bmr.workspace_bytes(n, p, nnz=nnz, precision="relaxed")
+    relaxed = blocks + 34 * n * p * 4 + 2 * n * 4 + nnz * 4
+    assert relaxed < wr < relaxed + (16 << 20)
+    # its switch level lies in (tol, 1) (0: the default); not with kept candidates
+    for field, value in [("relax_tol", -1e-3), ("relax_tol", 1e-8), ("relax_tol", 1.0), ("flags", bmr.FLAG_RETAIN)]:
+        lib.bmr_default_opts(ctypes.byref(o))
+        o.precision = bmr.PREC_RELAXED
+        setattr(o, field, value)
+        assert lib.bmr_workspace_bytes(10, 28, 4, ctypes.byref(o), ctypes.byref(out)) == bmr.INVALID_ARG
+    lib.bmr_default_opts(ctypes.byref(o))
+    o.precision, o.relax_tol = bmr.PREC_RELAXED, 1e-3
+    assert lib.bmr_workspace_bytes(10, 28, 4, ctypes.byref(o), ctypes.byref(out)) == 0
 
 
 def test_invalid_arguments_rejected_on_host(lib):
