@@ -58,6 +58,8 @@ KERNEL_SOURCES = {
     "pass1_spmm_gram": ["paper_1301_2102_amd/csrc/kernels_spmm.hip", "paper_1301_2102_amd/csrc/bmr_internal.hpp"],
     "pass2_update": ["paper_1301_2102_amd/csrc/kernels_stream.hip", "paper_1301_2102_amd/csrc/bmr_internal.hpp"],
 }
+for _q in (1, 8, 16):  # the standalone block operator (k_spmm<q, double>)
+    KERNEL_SOURCES[f"spmm_p{_q}"] = KERNEL_SOURCES["pass1_spmm_gram"]
 
 
 def measured_traffic(workload, kernel):
@@ -270,7 +272,8 @@ def main():
     log(f"[bench] timed {args.steps} solves: {ms_per_step:.2f} ms each, {info.status_name}, "
         f"j={info.band_iters}, blocks={info.block_iters}")
     beta = np.linalg.norm(B, axis=0)
-    explicit = float((bmr.residual(Ad, Bd, X) / beta).max())
+    explicit_cols = bmr.residual(Ad, Bd, X) / beta
+    explicit = float(explicit_cols.max())
 
     # per-kernel durations inside a solve (HIP events on the solve stream)
     _, pinfo = bmr.solve(Ad, Bd, tol=tol, max_iter=max_iter, workspace=ws, profile=True)
@@ -324,6 +327,10 @@ def main():
             key = f"p{q}" if esz == 8 else f"p{q}_fp32"
             spmm[key] = {"avg_ms": round(ms, 5), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
                          "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": b}
+            if esz == 8:  # HBM bytes from the committed counters, over this run's time
+                tb = measured_traffic(args.workload, f"spmm_p{q}")
+                spmm[key]["traffic"] = tb
+                spmm[key]["traffic_frac"] = round(tb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tb else None
             del V, W
     del val32
     log(f"[bench] spmm: {spmm}")
@@ -412,6 +419,26 @@ def main():
         rand = throughput_leg(bmr, torch, "rand-1m-p16", dev, args.rand_block_iters)
         log(f"[bench] random matrix: {rand}")
 
+    # achievable bandwidth of a plain device copy (context for the fractions)
+    csrc = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    cdst = torch.empty_like(csrc)
+    for _ in range(3):
+        cdst.copy_(csrc)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cdst.copy_(csrc)
+    e1.record()
+    torch.cuda.synchronize()
+    cms = e0.elapsed_time(e1) / 10
+    copy_bw = {"bytes": 2 * csrc.numel() * 8, "avg_ms": round(cms, 4),
+               "GB/s": round(2 * csrc.numel() * 8 / (cms * 1e-3) / 1e9, 1),
+               "frac": round(2 * csrc.numel() * 8 / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "what": "torch copy_ of 1 GiB float64 (read + write), mean of 10"}
+    del csrc, cdst
+    log(f"[bench] device copy: {copy_bw}")
+
     if args.copy_ref_mib:
         src = torch.empty(args.copy_ref_mib << 17, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -446,10 +473,12 @@ def main():
         "block_iters": info.block_iters,
         "res_rec_max": float(info.res_rec.max()),
         "res_explicit_max": explicit,
+        "res_explicit": [float(v) for v in explicit_cols],
         "res_explicit_stats_max": float(info.res_explicit.max()),
         "roofline": roofline,
         "kernels": kernels,
         "spmm": spmm,
+        "copy_bandwidth": copy_bw,
         "cpu_baseline": cpu,
         "mixed": mixed,
         "relaxed": relaxed,
