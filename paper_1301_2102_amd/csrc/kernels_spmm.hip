@@ -303,6 +303,12 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
       // the two lead chunks form one batch: every gathered load of the
       // batch is issued before the first of them is consumed, so a row of up
       // to 2 * LPR entries costs one round trip to memory for its V rows
+      // A wavefront about to issue its gather runs at raised priority until
+      // the loads are out, so that the SIMD's arbiter lets the memory phase
+      // of one wavefront start before the arithmetic of the others (pass 1
+      // at 128^3: p = 8 0.1516 -> 0.1489 ms, p = 16 0.3908 -> 0.3873 ms;
+      // with one lane per row it cost 2%, so that path keeps the default).
+      __builtin_amdgcn_s_setprio(2);
       if constexpr (OWN) load_own<CPL>(own, ov);
       const int cnt = e - s;
       T x[2 * LPR][CPL];
@@ -320,6 +326,7 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
         load_lead<LPR>(ci, va, s_nx, e_nx, c, *lead);
         mid();
       }
+      __builtin_amdgcn_s_setprio(0);
       // the values are passed round after the loads are in flight
 #pragma unroll
       for (int u = 0; u < 2 * LPR; ++u) {
@@ -347,6 +354,7 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
       for (int h = 0; h < LPR / U; ++h) {
         if (h > 0 && h * U >= cnt) break;
         T x[U][CPL];
+        __builtin_amdgcn_s_setprio(2);  // as for the lead entries above
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int cq = grp_bcast<LPR>(col, h * U + u);
@@ -357,6 +365,7 @@ __device__ inline void gather_se(const int32_t* __restrict__ ci, const T* __rest
             for (int k = 0; k < CPL; ++k) x[u][k] = T(0);
           }
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const T vq = grp_bcast<LPR>(v, h * U + u);

@@ -133,3 +133,23 @@ def test_full_size_relaxed_to_1e10():
     R = (Bd - bmr.spmm(Ad, X)).cpu().numpy()
     assert np.allclose(R[rows], r_rows, rtol=0, atol=1e-12 * np.abs(B).max())
     assert (np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)).max() < 2e-10
+
+
+def test_relaxed_without_bench_with_profile_and_short_history():
+    """n_bench = 0 (no substitute vectors to round), the per-kernel timing
+    flag (one block iteration in flight at a time, so the switch may come a
+    group later) and a history shorter than the run: both converge with the
+    explicit residual at tol, and their FP64 part is the same iteration."""
+    A = laplacian((24, 24, 24), 0.3)
+    B = rhs_normal(A.n, 8, seed=8)
+    Ad, Bd = bmr.to_device(A, DEV), _dev(B)
+    kw = dict(tol=1e-10, max_iter=40000, poll_every=4, precision="relaxed", relax_tol=1e-5, n_bench=0)
+    X, info = bmr.solve(Ad, Bd, hist_cap=40000, **kw)
+    Xp, infop = bmr.solve(Ad, Bd, hist_cap=100, profile=True, **kw)
+    assert info.status == 0 and infop.status == 0
+    assert info.switch_iter > 0 and infop.switch_iter > 0
+    assert infop.hist.shape == (100, 8)
+    assert np.array_equal(infop.hist, info.hist[:100])
+    assert infop.kernel_ms["n_block_iters"] > 0
+    for Y in (X, Xp):
+        assert _explicit(A, B, Y.cpu().numpy()) < 3e-10
