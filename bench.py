@@ -224,7 +224,8 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=400)
     ap.add_argument("--rand-block-iters", type=int, default=200,
                     help="block iterations of the random-matrix throughput leg (0: skip)")
-    ap.add_argument("--spmm-reps", type=int, default=50)
+    ap.add_argument("--spmm-reps", type=int, default=50, help="graph-replayed launches (mean)")
+    ap.add_argument("--spmm-median-reps", type=int, default=100, help="event-timed launches (median)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for hardware byte counters)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
@@ -323,10 +324,21 @@ def main():
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.spmm_reps
             del graph
+            # and the median of individually timed launches
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.spmm_median_reps)]
+            for a0, a1 in evs:
+                a0.record()
+                op()
+                a1.record()
+            torch.cuda.synchronize()
+            med = float(np.median([a0.elapsed_time(a1) for a0, a1 in evs]))
             b = kernel_bytes(A, q, 0, esz)["spmm"]
             key = f"p{q}" if esz == 8 else f"p{q}_fp32"
             spmm[key] = {"avg_ms": round(ms, 5), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
-                         "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": b}
+                         "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": b,
+                         "median_ms": round(med, 5),
+                         "median_frac": round(b / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             if esz == 8:  # HBM bytes from the committed counters, over this run's time
                 tb = measured_traffic(args.workload, f"spmm_p{q}")
                 spmm[key]["traffic"] = tb
@@ -461,6 +473,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
+        "solve_ms_median": round(float(np.median([i.time_ms for i in infos])), 3),
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
