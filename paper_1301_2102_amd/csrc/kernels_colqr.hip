@@ -196,7 +196,7 @@ __global__ __launch_bounds__(WG) void k_qr_dots(int step, int mode, int l, int p
     }
   }
   __syncthreads();
-  if (threadIdx.x < m) {
+  if ((int)threadIdx.x < m) {
     const int e = threadIdx.x;
     part[(size_t)e * n_wg + blockIdx.x] = (sh[0][e] + sh[1][e]) + (sh[2][e] + sh[3][e]);
   }

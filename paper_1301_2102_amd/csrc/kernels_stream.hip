@@ -454,8 +454,8 @@ __global__ __launch_bounds__(WG) void k_coldots(const T* Y, int ldy, int yc, con
     }
   }
   __syncthreads();
-  if (threadIdx.x <= m) {
-    const int r = threadIdx.x < m ? threadIdx.x : MAXP;
+  if ((int)threadIdx.x <= m) {
+    const int r = (int)threadIdx.x < m ? (int)threadIdx.x : MAXP;
     part[(size_t)blockIdx.x * (m + 1) + threadIdx.x] = (sh[0][r] + sh[1][r]) + (sh[2][r] + sh[3][r]);
   }
 }
